@@ -1,0 +1,319 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test names what fixes the expected value: brute force on tiny inputs,
+closed forms, invariants of the operator, library routines on an independently
+assembled matrix, and the claims the paper makes about CGLS and LSQR.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import kct_inputs as ki
+import oracle
+from tests import bruteforce as bf
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ operator
+
+@pytest.fixture(scope="module", params=["base", "offcenter", "aniso", "odd"])
+def t16_pair(request):
+    g = ki.t16(request.param)
+    return g, bf.matrix(g)
+
+
+def test_bruteforce_matrix_forward(t16_pair):
+    """A x from the oracle's Siddon traversal equals the pair-by-pair slab matrix (Eq. 1)."""
+    g, A = t16_pair
+    for seed in (1, 2):
+        x = ki.random_volume(g, seed)
+        assert rel(oracle.project(g, x), A @ x.ravel()) < 1e-12
+    x = ki.phantom(g, 6, 7, dtype=np.float64)
+    assert rel(oracle.project(g, x), A @ x.ravel()) < 1e-12
+
+
+def test_bruteforce_matrix_transpose(t16_pair):
+    """A^T y from the oracle's slab-parallel scatter equals the brute-force transpose (Eq. 2)."""
+    g, A = t16_pair
+    for seed in (3, 4):
+        y = ki.random_projections(g, seed)
+        assert rel(oracle.backproject(g, y), A.T @ y.ravel()) < 1e-12
+
+
+def test_bruteforce_structure(t16_pair):
+    """Same set of weights above rounding level (structural nonzeros) as brute force.
+    Pieces shorter than 1e-9 mm are rounding artefacts of coincident crossings."""
+    g, A = t16_pair
+    B = oracle.assemble(g)  # duplicate (ray, voxel) pieces are summed here
+    assert B.nnz <= oracle.count_nnz(g) <= B.nnz + 64
+    assert (B.data > 1e-9).sum() == (A.data > 1e-9).sum()
+    assert abs(B - A).max() < 1e-12
+
+
+def test_sampled_rays_and_voxels(t16_pair):
+    g, A = t16_pair
+    x = ki.random_volume(g, 5)
+    y = ki.random_projections(g, 6)
+    rng = np.random.default_rng(0)
+    rays = rng.choice(g.n_rays, 64, replace=False)
+    vox = rng.choice(g.n_vox, 64, replace=False)
+    np.testing.assert_allclose(oracle.project_rays(g, x, rays), (A @ x.ravel())[rays], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(oracle.backproject_voxels(g, y, vox), (A.T @ y.ravel())[vox], rtol=1e-12,
+                               atol=1e-12)
+
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "aniso"])
+def test_uniform_volume_is_box_chord(variant):
+    """x = 1 gives the chord of each ray through the whole volume box (closed form)."""
+    g = ki.t16(variant)
+    lo = np.array([g.cx - g.nx * g.vx / 2, g.cy - g.ny * g.vy / 2, g.cz - g.nz * g.vz / 2])
+    hi = lo + np.array([g.nx * g.vx, g.ny * g.vy, g.nz * g.vz])
+    b = oracle.project(g, np.ones(g.vol_shape))
+    np.testing.assert_allclose(b, bf.box_chord(g, lo, hi), rtol=1e-13, atol=1e-12)
+    assert b.max() > 0
+
+
+@pytest.mark.parametrize("vox", [(0, 0, 0), (5, 9, 3), (15, 15, 15), (8, 8, 8), (2, 13, 11)])
+def test_single_voxel_is_box_chord(vox):
+    """x = e_j gives the chord of each ray through one voxel box (closed form)."""
+    g = ki.t16("offcenter")
+    ix, iy, iz = vox
+    x = np.zeros(g.vol_shape)
+    x[iz, iy, ix] = 1.0
+    lo = np.array([g.cx - g.nx * g.vx / 2 + ix * g.vx, g.cy - g.ny * g.vy / 2 + iy * g.vy,
+                   g.cz - g.nz * g.vz / 2 + iz * g.vz])
+    hi = lo + np.array([g.vx, g.vy, g.vz])
+    np.testing.assert_allclose(oracle.project(g, x), bf.box_chord(g, lo, hi), rtol=1e-13, atol=1e-13)
+
+
+def test_orientation_sign():
+    """At view angle 0 an object at +y lands on +u (magnification SDD/SID) and +z on +v."""
+    g = ki.t16().replace(n_views=1)
+    x = np.zeros(g.vol_shape)
+    x[8, 12, 8] = 1.0  # voxel centre at (+0.5, +4.5, +0.5) mm
+    b = oracle.project(g, x)[0]
+    iv, iu = np.unravel_index(np.argmax(b), b.shape)
+    u = (iu - (g.nu - 1) / 2) * g.du
+    v = (iv - (g.nv - 1) / 2) * g.dv
+    mag = g.sdd / (g.sid - 0.5)
+    assert abs(u - 4.5 * mag) <= 1.0 and abs(v - 0.5 * mag) <= 1.0
+
+
+def test_rotation_symmetry():
+    """Rotating the volume by +90 degrees about z and every view angle by +90 degrees
+    leaves the projections unchanged (rotation sense of the orbit)."""
+    g = ki.t16().replace(n_views=5, angle0=0.3, arc=1.0)
+    g90 = g.replace(angle0=0.3 + math.pi / 2)
+    x = ki.random_volume(g, 9)
+    xr = np.rot90(x, k=-1, axes=(1, 2))  # new[iy, ix] = old[n-1-ix, iy]
+    assert rel(oracle.project(g90, xr.copy()), oracle.project(g, x)) < 1e-12
+
+
+def test_linearity_and_nonnegativity():
+    g = ki.t16("offcenter")
+    x1, x2 = ki.random_volume(g, 11), ki.random_volume(g, 12)
+    a, b = 1.7, -0.4
+    assert rel(oracle.project(g, a * x1 + b * x2),
+               a * oracle.project(g, x1) + b * oracle.project(g, x2)) < 1e-12
+    xp = np.abs(x1)
+    assert oracle.project(g, xp).min() >= 0.0
+
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "odd"])
+def test_adjoint_dot_product(variant):
+    """<A x, y> = <x, A^T y>."""
+    g = ki.t16(variant)
+    x = ki.random_volume(g, 21)
+    y = ki.random_projections(g, 22)
+    lhs = float((oracle.project(g, x) * y).sum())
+    rhs = float((x * oracle.backproject(g, y)).sum())
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + np.linalg.norm(x) * np.linalg.norm(y))
+
+
+def test_ellipsoid_line_integrals_converge_linearly():
+    """A applied to a 4^3-supersampled voxelised ellipsoid tends to the analytic
+    ellipsoid line integrals with error O(h): halving the voxel size halves the error."""
+    errs = []
+    for n in (16, 32, 64):
+        vox = 32.0 / n
+        g = ki.ConeGeometry(n, n, n, vox, vox, vox, n_views=8, nu=40, nv=40, du=1.6, dv=1.6,
+                            cx=0.7, cy=-1.1, cz=0.4, angle0=0.2)
+        q = np.array([0.3, -0.5, 0.6, 0.55])
+        q /= np.linalg.norm(q)
+        e = ki.Ellipsoid(np.array([1.5, -2.0, 1.0]), np.array([11.0, 7.0, 9.0]), ki._quat_to_rot(q), 1.0)
+        x = ki.voxelize(g, [e], supersample=4, dtype=np.float64)
+        ref = bf.ellipsoid_chords(g, e)
+        errs.append(rel(oracle.project(g, x), ref))
+    assert errs[0] < 0.15 and errs[-1] < 0.04
+    for a, b in zip(errs, errs[1:]):
+        assert 1.4 < a / b < 2.8, errs
+
+
+# ------------------------------------------------------------------ CGLS / LSQR
+
+def small_geom():
+    return ki.ConeGeometry(8, 8, 8, 2.0, 2.0, 2.0, n_views=8, nu=24, nv=20, du=1.5, dv=1.5,
+                           cx=0.3, cy=-0.2, cz=0.1)
+
+
+@pytest.fixture(scope="module")
+def small_problem():
+    g = small_geom()
+    A = bf.matrix(g)
+    xt = ki.phantom(g, 5, 31, dtype=np.float64)
+    b = (A @ xt.ravel()).reshape(g.proj_shape)
+    b = ki.gaussian_noise(b, 0.01, 32)
+    return g, A, b
+
+
+def krylov_minimiser(A, b, x0, K):
+    """argmin |b - A x| over x0 + span{r0, (A^T A) r0, ..., (A^T A)^(K-1) r0}, dense FP64.
+    The basis is built by Lanczos with full re-orthogonalisation."""
+    r0 = A.T @ (b - A @ x0)
+    V = np.zeros((A.shape[1], K))
+    v = r0 / np.linalg.norm(r0)
+    for j in range(K):
+        for _ in range(2):
+            v = v - V[:, :j] @ (V[:, :j].T @ v)
+        v = v / np.linalg.norm(v)
+        V[:, j] = v
+        v = A.T @ (A @ v)
+    AV = A @ V
+    y, *_ = np.linalg.lstsq(AV, b - A @ x0, rcond=None)
+    return x0 + V @ y
+
+
+def test_cgls_first_iterate_closed_form(small_problem):
+    """x_1 = x0 + alpha r0, r0 = A^T (b - A x0), alpha = |r0|^2 / |A r0|^2."""
+    g, A, b = small_problem
+    bb = b.ravel()
+    x0 = ki.random_volume(g, 33).ravel() * 0.1
+    r0 = A.T @ (bb - A @ x0)
+    alpha = (r0 @ r0) / np.linalg.norm(A @ r0) ** 2
+    res = oracle.cgls(g, b, 1, x0=x0)
+    assert res.iterations == 1
+    assert rel(res.x, x0 + alpha * r0) < 1e-12
+    assert abs(res.nb - np.linalg.norm(bb - A @ res.x.ravel())) < 1e-10 * res.nb
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5, 6])
+def test_cgls_and_lsqr_are_krylov_minimisers(small_problem, K):
+    """Both iterates minimise the residual over the same Krylov space (brute force)."""
+    g, A, b = small_problem
+    x0 = ki.random_volume(g, 34).ravel() * 0.05
+    ref = krylov_minimiser(A, b.ravel(), x0, K)
+    assert rel(oracle.cgls(g, b, K, x0=x0).x, ref) < 1e-9
+    assert rel(oracle.lsqr(g, b, K, x0=x0).x, ref) < 1e-9
+    assert rel(oracle.cgls(g, b, K).x, krylov_minimiser(A, b.ravel(), np.zeros(g.n_vox), K)) < 1e-9
+
+
+def test_printed_direction_update_is_not_cg(small_problem):
+    """The direction update as printed (d = d + beta r) leaves the Krylov minimiser,
+    which is why the oracle reads it as d = r + beta d."""
+    g, A, b = small_problem
+    ref = krylov_minimiser(A, b.ravel(), np.zeros(g.n_vox), 4)
+    assert rel(oracle.cgls(g, b, 4).x, ref) < 1e-9
+    assert rel(oracle.cgls(g, b, 4, literal_update=True).x, ref) > 1e-3
+
+
+@pytest.mark.parametrize("K", [10, 20])
+def test_lsqr_matches_scipy(small_problem, K):
+    """The oracle's LSQR and CGLS against scipy.sparse.linalg.lsqr on the brute-force matrix."""
+    g, A, b = small_problem
+    ref = spla.lsqr(A, b.ravel(), damp=0.0, atol=0.0, btol=0.0, conlim=0.0, iter_lim=K)[0]
+    assert rel(oracle.lsqr(g, b, K).x, ref) < 1e-9
+    assert rel(oracle.cgls(g, b, K).x, ref) < 1e-8
+
+
+def test_cgls_matches_cg_on_normal_equations(small_problem):
+    """CGLS = CG on A^T A x = A^T b (Eq. 2), via scipy.sparse.linalg.cg."""
+    g, A, b = small_problem
+    K = 8
+    ATA = spla.aslinearoperator(A.T @ A)
+    ref, _ = spla.cg(ATA, A.T @ b.ravel(), x0=np.zeros(g.n_vox), rtol=0.0, atol=0.0, maxiter=K)
+    assert rel(oracle.cgls(g, b, K).x, ref) < 1e-8
+
+
+def test_cgls_lsqr_practically_identical():
+    """The paper reports that LSQR and CGLS give practically identical results on
+    CT data.  In FP64 they agree to 1e-8 while the Krylov basis stays orthogonal
+    (20 iterations here); at 40 iterations both have drifted from the exact
+    Krylov minimiser by loss of orthogonality, yet their discrepancies still
+    agree within 1 % and their iterates within 1 %."""
+    g = ki.config("c1").replace(nx=32, ny=32, nz=32, vx=2.0, vy=2.0, vz=2.0, n_views=30, nu=48, nv=48,
+                                du=2.0, dv=2.0)
+    xt = ki.phantom(g, 10, 101, dtype=np.float64)
+    b = ki.gaussian_noise(oracle.project(g, xt), 0.005, 1000101)
+    c = oracle.cgls(g, b, 20)
+    s = oracle.lsqr(g, b, 20)
+    assert c.iterations == s.iterations == 20
+    assert rel(c.x, s.x) < 1e-8
+    np.testing.assert_allclose(c.history, s.history, rtol=1e-8)
+    c = oracle.cgls(g, b, 40)
+    s = oracle.lsqr(g, b, 40)
+    assert rel(c.x, s.x) < 1e-2
+    np.testing.assert_allclose(c.history, s.history, rtol=1e-2)
+
+
+@pytest.fixture(scope="module")
+def c1_small():
+    g = ki.config("c1").replace(nx=32, ny=32, nz=32, vx=2.0, vy=2.0, vz=2.0, n_views=45, nu=48, nv=48,
+                                du=2.0, dv=2.0)
+    xt = ki.phantom(g, 10, 101, dtype=np.float64)
+    b = oracle.project(g, xt)
+    return g, xt, b
+
+
+def test_cgls_monotone(c1_small):
+    """CG on the normal equations: |b - A x_k| non-increasing and |x_k - x0| non-decreasing."""
+    g, xt, b = c1_small
+    res = oracle.cgls(g, b, 12)
+    h = res.history
+    assert np.all(np.diff(h) <= 1e-14)
+    norms = [np.linalg.norm(oracle.cgls(g, b, k).x) for k in range(1, 9)]
+    assert np.all(np.diff(norms) >= -1e-12)
+
+
+def test_cgls_updated_residual_drift(c1_small):
+    """The paper finds the updated and the recomputed discrepancy differ by less
+    than 0.0001 % after 10 iterations."""
+    g, xt, b = c1_small
+    res = oracle.cgls(g, b, 10)
+    true_nb = np.linalg.norm(b - oracle.project(g, res.x))
+    assert abs(res.nb - true_nb) / true_nb < 1e-6
+
+
+def test_cgls_converges_on_consistent_data(c1_small):
+    """Loose sanity check of the paper's convergence finding: on noise-free,
+    consistent data the relative discrepancy falls below 1 % within a few dozen
+    iterations and keeps falling."""
+    g, xt, b = c1_small
+    res = oracle.cgls(g, b, 30)
+    e = res.history
+    assert e[-1] < 0.01
+    assert np.argmax(e < 0.01) < 30
+
+
+def test_cgls_edge_cases():
+    g = small_geom()
+    zero = np.zeros(g.proj_shape)
+    res = oracle.cgls(g, zero, 5)
+    assert res.iterations == 0 and res.stop_reason == oracle.STOP_BREAKDOWN and not res.x.any()
+    res = oracle.lsqr(g, zero, 5)
+    assert res.iterations == 0 and res.stop_reason == oracle.STOP_BREAKDOWN and not res.x.any()
+    b = oracle.project(g, ki.phantom(g, 3, 1, dtype=np.float64))
+    x0 = ki.random_volume(g, 2)
+    res = oracle.cgls(g, b, 0, x0=x0)
+    assert res.iterations == 0 and np.array_equal(res.x.ravel(), x0.ravel())
+    # tolerance stop
+    res = oracle.cgls(g, b, 50, err=0.2)
+    assert res.stop_reason == oracle.STOP_TOL and res.history[-1] <= 0.2 and res.iterations < 50
+    res = oracle.lsqr(g, b, 50, err=0.2)
+    assert res.stop_reason == oracle.STOP_TOL and res.history[-1] <= 0.2 and res.iterations < 50
