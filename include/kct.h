@@ -1,0 +1,180 @@
+/*
+ * kct.h -- C ABI of the MI355X (gfx950) cone-beam projector pair and the CGLS /
+ * LSQR solvers built around it.
+ *
+ * Method: Kulvait & Rose, "Software Implementation of the Krylov Methods Based
+ * Reconstruction for the 3D Cone Beam CT Operator" (Fully3D 2021,
+ * arXiv 2110.13526).  The operator A maps a voxel volume x to projection data
+ * b = A x (Section 2, Eq. 1); the reconstruction solves the least-squares
+ * problem through the normal equations A^T A x = A^T b (Section 2, Eq. 2) with
+ * CGLS (Section 2, Algorithm 1, CGLS with delayed residual computation) or LSQR
+ * (Section 2; Paige & Saunders 1982).  The projector is the Siddon ray model
+ * (Section 3): w_ij is the length in mm of the segment from the source to the
+ * centre of detector pixel i that lies inside voxel j.  A and A^T evaluate the
+ * same weight function on the same single-precision ray parameters, so A^T is
+ * the exact transpose of A up to accumulation rounding.
+ *
+ * Geometry convention (the paper fixes only SID, SDD, pixel pitch and the
+ * number of views, Section 4): world frame in mm, rotation axis +z; view k has
+ * source s = (SID cos t_k, SID sin t_k, 0), detector centre s - SDD (cos t_k,
+ * sin t_k, 0), detector axes e_u = (-sin t_k, cos t_k, 0) and e_v = (0, 0, 1);
+ * pixel (iv, iu) has its centre at u = (iu - (nu-1)/2) du + off_u,
+ * v = (iv - (nv-1)/2) dv + off_v.  Voxel (ix, iy, iz) spans
+ * [cx - nx vx/2 + ix vx, ... + vx] and likewise in y and z (off-centre volumes
+ * are allowed, Section 3).  The volume must lie strictly between the source and
+ * the detector for every view.
+ *
+ * Memory layout (dense, no padding): volume x[iz][iy][ix] (ix fastest),
+ * projections b[k][iv][iu] (iu fastest).  Storage type is chosen per call
+ * (kct_dtype); ray and voxel accumulation is single precision, solver scalars
+ * (norms, step lengths, Givens rotations) are double precision on the device.
+ *
+ * Conventions for every function below:
+ *  - Data pointers are DEVICE pointers of the current HIP device unless marked
+ *    (host).  Buffers are contiguous, 16-byte aligned and must not alias.
+ *  - Outputs are overwritten, never accumulated into.
+ *  - Work is enqueued on the given stream (0 = legacy default stream) and is
+ *    asynchronous unless stated otherwise.
+ *  - Arguments are validated before anything is enqueued.  On failure nothing
+ *    runs, a status other than KCT_OK is returned and kct_last_error() holds a
+ *    message for the calling thread.  No function aborts or throws.
+ *  - The library allocates only the geometry's small tables (kct_geometry_
+ *    create); every large buffer (volumes, projections, workspaces) belongs to
+ *    the caller.
+ */
+#ifndef KCT_H
+#define KCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KCT_OK = 0,
+    KCT_ERR_INVALID_ARG = 1, /* null pointer, bad size, degenerate geometry        */
+    KCT_ERR_UNSUPPORTED = 2, /* storage type or option not available               */
+    KCT_ERR_HIP = 3,         /* a HIP runtime call failed                           */
+    KCT_ERR_WORKSPACE = 4,   /* workspace missing or smaller than required          */
+    KCT_ERR_NUMERIC = 5      /* a solver norm became NaN or Inf                     */
+} kct_status;
+
+/* Storage type of volumes, projections and workspace vectors. */
+typedef enum { KCT_F32 = 0, KCT_BF16 = 1, KCT_F16 = 2 } kct_dtype;
+
+/* Voxel grid: counts, voxel size [mm] and the volume centre [mm] (off-centre
+ * reconstruction, Section 3). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double vx, vy, vz;
+    double cx, cy, cz;
+} kct_volume_desc;
+
+/* Circular cone-beam orbit and flat detector (Section 4 gives SID, SDD, pixel
+ * pitch and number of views).  View angles are t_k = angle0 + k * arc / n_views
+ * unless `angles` (host, n_views values in radians) is given. */
+typedef struct {
+    int32_t n_views;
+    double angle0, arc;
+    const double *angles; /* (host, optional) */
+    double sid, sdd;      /* source-isocentre and source-detector distance [mm] */
+    int32_t nu, nv;       /* detector columns (u) and rows (v) */
+    double du, dv;        /* pixel pitch [mm] */
+    double off_u, off_v;  /* detector offset [mm] */
+} kct_cone_desc;
+
+/* Opaque geometry handle.  It owns small device tables on the device that was
+ * current at creation; use it only with that device current. */
+typedef struct kct_geometry_s *kct_geometry;
+
+/* Validate the description and upload the per-view / per-column / per-row ray
+ * tables (computed in double precision on the host and rounded once to single).
+ * Errors: KCT_ERR_INVALID_ARG for non-positive sizes or pitches, SDD <= SID, or
+ * a volume that is not strictly between source and detector; KCT_ERR_HIP if the
+ * upload fails.  Synchronous. */
+kct_status kct_geometry_create(const kct_volume_desc *vol, const kct_cone_desc *cone, kct_geometry *out);
+
+/* Free the tables (NULL is ignored).  The caller must ensure no enqueued work
+ * still uses the geometry. */
+void kct_geometry_destroy(kct_geometry g);
+
+/* Number of voxels (n) and rays (m) of A in R^{m x n} (Section 2, Eq. 1). */
+kct_status kct_geometry_dims(kct_geometry g, int64_t *n_vox, int64_t *n_rays);
+
+/* Bytes of workspace kct_project needs for its best layout: one volume in
+ * the storage type (a copy with x and y swapped, read by views whose rays run
+ * mostly along x). */
+kct_status kct_project_workspace_size(kct_geometry g, kct_dtype dtype, size_t *bytes);
+
+/* Forward projection b := A x (Section 2, Eq. 1; standalone projection,
+ * Section 3).  x: n_vox elements, b: n_rays elements, both of `dtype`.  `ws`
+ * may be NULL (then x is read in its own layout by every view, which is
+ * correct but slower); otherwise ws_bytes must be at least
+ * kct_project_workspace_size.  Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE,
+ * HIP. */
+kct_status kct_project(kct_geometry g, kct_dtype dtype, const void *x, void *b, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
+
+/* Backprojection x := A^T b (Section 2, Eq. 2; standalone backprojection,
+ * Section 3), the exact transpose of kct_project.  Voxel-driven gather: no
+ * atomics, deterministic.  Errors: INVALID_ARG, UNSUPPORTED, HIP. */
+kct_status kct_backproject(kct_geometry g, kct_dtype dtype, const void *b, void *x, hipStream_t stream);
+
+/* Solver options (Algorithm 1 inputs besides b and x0). */
+typedef struct {
+    int32_t max_iter;   /* K >= 0; K = 0 returns x0 unchanged                           */
+    double err_tol;     /* ERR >= 0: stop once NB <= ERR * NB0 (NB0 = |b|, Eq. 3)        */
+    int32_t x0_is_zero; /* nonzero: x is not read, the solve starts from x0 = 0          */
+    double *history;    /* (device, optional) max_iter doubles: NB_i / NB0 per iteration  */
+} kct_solve_opts;
+
+/* Stop reasons. */
+enum { KCT_STOP_MAXITER = 0, KCT_STOP_TOL = 1, KCT_STOP_BREAKDOWN = 2, KCT_STOP_NUMERIC = 3 };
+
+/* Solver result (host).  For CGLS nb is the updated discrepancy norm NB of
+ * Algorithm 1; for LSQR it is the estimate |phibar| of |b - A x|. */
+typedef struct {
+    int32_t iterations;  /* i of Algorithm 1 (updates of x)                   */
+    double nb0, nb;      /* |b| and the final discrepancy norm                 */
+    double nr2;          /* CGLS: last |A^T e|^2; LSQR: last alpha^2           */
+    int32_t stop_reason; /* KCT_STOP_*                                          */
+} kct_solve_info;
+
+enum { KCT_SOLVER_CGLS = 0, KCT_SOLVER_LSQR = 1 };
+
+/* Workspace bytes for a solver.  CGLS holds d, r and a transposed copy of d
+ * (volumes) and e, p (projections): the paper's three volumes and three
+ * projection vectors with x and b (Section 5) plus the transposed copy, and a
+ * small block of double-precision scalars and reduction partials.  LSQR holds
+ * v, w and a transposed v (volumes) and u (projections). */
+kct_status kct_solver_workspace_size(kct_geometry g, kct_dtype dtype, int32_t solver, size_t *bytes);
+
+/* CGLS with delayed residual computation (Section 2, Algorithm 1), with the
+ * direction update d = r + beta d.  b: n_rays elements; x: n_vox elements,
+ * x0 on entry (unless opts->x0_is_zero), x_K on return.  Breakdown (NR2 = 0 or
+ * NP2 = 0, e.g. b = 0) stops with the current x.  The whole iteration runs on
+ * the device without host synchronisation; the call synchronises `stream` once
+ * at the end to fill *info (host).  Errors: INVALID_ARG, UNSUPPORTED,
+ * WORKSPACE, HIP; KCT_ERR_NUMERIC when NB became NaN/Inf (info is still
+ * filled). */
+kct_status kct_cgls_solve(kct_geometry g, kct_dtype dtype, const void *b, void *x, const kct_solve_opts *opts,
+                          void *ws, size_t ws_bytes, kct_solve_info *info, hipStream_t stream);
+
+/* LSQR (Section 2, Paige & Saunders 1982): Golub-Kahan bidiagonalisation with
+ * Givens QR, iterations aligned with CGLS (K products with A and K with A^T).
+ * Same arguments, ownership and errors as kct_cgls_solve. */
+kct_status kct_lsqr_solve(kct_geometry g, kct_dtype dtype, const void *b, void *x, const kct_solve_opts *opts,
+                          void *ws, size_t ws_bytes, kct_solve_info *info, hipStream_t stream);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *kct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KCT_H */

@@ -1,0 +1,253 @@
+"""MI355X cone-beam projector pair and Krylov solvers (Kulvait & Rose, arXiv 2110.13526).
+
+Thin Python binding over the C ABI of ``include/kct.h``: every step of the
+projectors and of CGLS / LSQR runs in the HIP kernels of ``libkct.so``; this
+module only checks tensors, allocates outputs and workspaces with torch, and
+passes device pointers and the current HIP stream.
+
+    g = Geometry(nx=..., ..., n_views=..., nu=..., nv=..., du=..., dv=...)
+    b = project(g, x)            # b = A x           (Section 2, Eq. 1)
+    r = backproject(g, b)        # r = A^T b         (Section 2, Eq. 2)
+    x, info = cgls(g, b, K)      # Algorithm 1
+    x, info = lsqr(g, b, K)
+
+Volumes are torch tensors of shape (nz, ny, nx), projections (n_views, nv, nu),
+on the GPU, contiguous, with dtype float32, bfloat16 or float16 (storage type;
+accumulation is single precision and solver scalars double precision).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import KctError, STOP_BREAKDOWN, STOP_MAXITER, STOP_NUMERIC, STOP_TOL
+
+__all__ = ["Geometry", "project", "backproject", "cgls", "lsqr", "SolveInfo", "KctError",
+           "STOP_MAXITER", "STOP_TOL", "STOP_BREAKDOWN", "STOP_NUMERIC"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t == torch.float32:
+        return _lib.KCT_F32
+    if t == torch.bfloat16:
+        return _lib.KCT_BF16
+    if t == torch.float16:
+        return _lib.KCT_F16
+    raise TypeError(f"unsupported storage dtype {t} (float32, bfloat16 or float16)")
+
+
+def _stream_handle(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Geometry:
+    """Cone-beam geometry handle (owns the device ray tables of one GPU).
+
+    Lengths in mm; view angles t_k = angle0 + k * arc / n_views unless
+    ``angles`` is given (radians).  See include/kct.h for the convention.
+    """
+
+    FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "n_views", "nu", "nv", "du", "dv", "sid", "sdd", "cx", "cy",
+              "cz", "off_u", "off_v", "angle0", "arc")
+
+    def __init__(self, nx, ny, nz, vx, vy, vz, n_views, nu, nv, du, dv, sid=500.0, sdd=1000.0, cx=0.0, cy=0.0,
+                 cz=0.0, off_u=0.0, off_v=0.0, angle0=0.0, arc=2.0 * math.pi,
+                 angles: Optional[Sequence[float]] = None, device=None):
+        torch = _torch()
+        L = _lib.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.vx, self.vy, self.vz = float(vx), float(vy), float(vz)
+        self.n_views, self.nu, self.nv = int(n_views), int(nu), int(nv)
+        self.du, self.dv, self.sid, self.sdd = float(du), float(dv), float(sid), float(sdd)
+        self.cx, self.cy, self.cz = float(cx), float(cy), float(cz)
+        self.off_u, self.off_v, self.angle0, self.arc = float(off_u), float(off_v), float(angle0), float(arc)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
+                                   torch.device(device).index or 0)
+        vol = _lib.VolumeDesc(self.nx, self.ny, self.nz, self.vx, self.vy, self.vz, self.cx, self.cy, self.cz)
+        self._angles = None
+        ang_ptr = None
+        if angles is not None:
+            arr = (ctypes.c_double * self.n_views)(*[float(a) for a in angles])
+            if len(angles) != self.n_views:
+                raise ValueError("len(angles) must equal n_views")
+            self._angles = arr
+            ang_ptr = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+        cone = _lib.ConeDesc(self.n_views, self.angle0, self.arc, ang_ptr, self.sid, self.sdd, self.nu, self.nv,
+                             self.du, self.dv, self.off_u, self.off_v)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(L.kct_geometry_create(ctypes.byref(vol), ctypes.byref(cone), ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_desc(cls, d, device=None):
+        """Build from any object with the geometry attributes (e.g. kct_inputs.ConeGeometry)."""
+        kw = {f: getattr(d, f) for f in cls.FIELDS}
+        ang = getattr(d, "explicit_angles", None)
+        return cls(**kw, angles=ang, device=device)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("geometry was closed")
+        return self._h
+
+    @property
+    def vol_shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def proj_shape(self):
+        return (self.n_views, self.nv, self.nu)
+
+    @property
+    def n_vox(self):
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_rays(self):
+        return self.n_views * self.nv * self.nu
+
+    def project_workspace_bytes(self, dtype):
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().kct_project_workspace_size(self.handle, _dtype_code(dtype), ctypes.byref(n)))
+        return n.value
+
+    def solver_workspace_bytes(self, dtype, solver):
+        n = ctypes.c_size_t()
+        code = {"cgls": _lib.KCT_SOLVER_CGLS, "lsqr": _lib.KCT_SOLVER_LSQR}[solver]
+        _lib.check(_lib.load().kct_solver_workspace_size(self.handle, _dtype_code(dtype), code, ctypes.byref(n)))
+        return n.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().kct_geometry_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_tensor(t, shape, name, device):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the geometry on {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    _dtype_code(t.dtype)
+
+
+def _workspace(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def project(g: Geometry, x, out=None, workspace=None, transposed_copy: bool = True):
+    """b = A x (forward projection).  Returns a (n_views, nv, nu) tensor of x's dtype.
+
+    With ``transposed_copy`` (default) the library first writes a copy of x with
+    x and y swapped into ``workspace`` (allocated here if None) so that views
+    whose rays run mostly along x read neighbouring addresses; without it every
+    view reads x in place (same result bit for bit, slower)."""
+    torch = _torch()
+    _check_tensor(x, g.vol_shape, "x", g.device)
+    if out is None:
+        out = torch.empty(g.proj_shape, dtype=x.dtype, device=g.device)
+    _check_tensor(out, g.proj_shape, "out", g.device)
+    if out.dtype != x.dtype:
+        raise TypeError("out must have x's dtype")
+    ws_ptr, ws_bytes = None, 0
+    if transposed_copy:
+        if workspace is None:
+            workspace = _workspace(g.project_workspace_bytes(x.dtype), g.device)
+        ws_ptr, ws_bytes = ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
+    with torch.cuda.device(g.device):
+        _lib.check(_lib.load().kct_project(g.handle, _dtype_code(x.dtype), ctypes.c_void_p(x.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), ws_ptr, ws_bytes,
+                                           _stream_handle(g.device)))
+    return out
+
+
+def backproject(g: Geometry, b, out=None):
+    """r = A^T b (backprojection, exact transpose of project)."""
+    torch = _torch()
+    _check_tensor(b, g.proj_shape, "b", g.device)
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=b.dtype, device=g.device)
+    _check_tensor(out, g.vol_shape, "out", g.device)
+    if out.dtype != b.dtype:
+        raise TypeError("out must have b's dtype")
+    with torch.cuda.device(g.device):
+        _lib.check(_lib.load().kct_backproject(g.handle, _dtype_code(b.dtype), ctypes.c_void_p(b.data_ptr()),
+                                               ctypes.c_void_p(out.data_ptr()), _stream_handle(g.device)))
+    return out
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    iterations: int
+    nb0: float
+    nb: float
+    nr2: float
+    stop_reason: int
+    history: Optional[object] = None
+
+
+def _solve(which, g, b, K, x0, err, history, workspace, out):
+    torch = _torch()
+    _check_tensor(b, g.proj_shape, "b", g.device)
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=b.dtype, device=g.device)
+    _check_tensor(out, g.vol_shape, "out", g.device)
+    if out.dtype != b.dtype:
+        raise TypeError("out must have b's dtype")
+    if x0 is not None:
+        _check_tensor(x0, g.vol_shape, "x0", g.device)
+        if x0.data_ptr() != out.data_ptr():
+            out.copy_(x0)
+    hist = torch.zeros(max(int(K), 1), dtype=torch.float64, device=g.device) if history else None
+    opts = _lib.SolveOpts(int(K), float(err), int(x0 is None), ctypes.c_void_p(hist.data_ptr()) if hist is not None
+                          else None)
+    if workspace is None:
+        workspace = _workspace(g.solver_workspace_bytes(b.dtype, which), g.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    info = _lib.SolveInfo()
+    fn = _lib.load().kct_cgls_solve if which == "cgls" else _lib.load().kct_lsqr_solve
+    with torch.cuda.device(g.device):
+        st = fn(g.handle, _dtype_code(b.dtype), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                ctypes.byref(opts), ctypes.c_void_p(workspace.data_ptr()), ws_bytes, ctypes.byref(info),
+                _stream_handle(g.device))
+    if st not in (_lib.KCT_OK, _lib.KCT_ERR_NUMERIC):
+        _lib.check(st)
+    res = SolveInfo(info.iterations, info.nb0, info.nb, info.nr2, info.stop_reason,
+                    hist[: info.iterations].clone() if hist is not None else None)
+    if st == _lib.KCT_ERR_NUMERIC:
+        raise KctError(st, _lib.load().kct_last_error().decode(errors="replace"))
+    return out, res
+
+
+def cgls(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None):
+    """CGLS with delayed residual computation (Algorithm 1): returns (x_K, SolveInfo)."""
+    return _solve("cgls", g, b, K, x0, err, history, workspace, out)
+
+
+def lsqr(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None):
+    """LSQR (Paige & Saunders), iterations aligned with CGLS: returns (x_K, SolveInfo)."""
+    return _solve("lsqr", g, b, K, x0, err, history, workspace, out)

@@ -1,0 +1,458 @@
+// capi.cpp -- the extern "C" entry points of kct.h: argument validation,
+// workspace layout and the CGLS / LSQR drivers (sequences of kernel launches on
+// the caller's stream, no host synchronisation until the final result read).
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kct_internal.h"
+
+namespace kct {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone, Geometry *g);
+
+namespace {
+
+size_t elem_size(kct_dtype t)
+{
+    switch (t) {
+    case KCT_F32: return 4;
+    case KCT_BF16: return 2;
+    case KCT_F16: return 2;
+    default: return 0;
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t nvox(const Geometry *g) { return (int64_t)g->dev.nx * g->dev.ny * g->dev.nz; }
+int64_t nrays(const Geometry *g) { return (int64_t)g->dev.nviews * g->dev.nv * g->dev.nu; }
+
+int64_t num_partials(const Geometry *g)
+{
+    int64_t a = forward_num_blocks(g->dev), b = backward_num_blocks(g->dev), c = stream_num_blocks();
+    int64_t m = a > b ? a : b;
+    return m > c ? m : c;
+}
+
+struct SolverLayout {
+    size_t scal, part, v0, v1, v2, p0, p1, total;
+};
+
+// [Scalars][partials][3 volumes][2 (CGLS) or 1 (LSQR) projections]
+SolverLayout solver_layout(const Geometry *g, kct_dtype t, int solver)
+{
+    SolverLayout L{};
+    size_t es = elem_size(t);
+    size_t V = align256((size_t)nvox(g) * es), P = align256((size_t)nrays(g) * es);
+    L.scal = 0;
+    L.part = align256(sizeof(Scalars));
+    L.v0 = L.part + align256((size_t)num_partials(g) * sizeof(double));
+    L.v1 = L.v0 + V;
+    L.v2 = L.v1 + V;
+    L.p0 = L.v2 + V;
+    L.p1 = L.p0 + P;
+    L.total = (solver == KCT_SOLVER_CGLS) ? L.p1 + P : L.p1;
+    return L;
+}
+
+kct_status check_geometry(kct_geometry h, const char *fn)
+{
+    if (!h) {
+        set_error(std::string(fn) + ": geometry is NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        set_error(std::string(fn) + ": hipGetDevice failed");
+        return KCT_ERR_HIP;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    if (dev != g->device) {
+        set_error(std::string(fn) + ": the current device differs from the device the geometry was created on");
+        return KCT_ERR_INVALID_ARG;
+    }
+    return KCT_OK;
+}
+
+kct_status check_dtype(kct_dtype t, const char *fn)
+{
+    if (elem_size(t) == 0) {
+        set_error(std::string(fn) + ": unknown storage type");
+        return KCT_ERR_UNSUPPORTED;
+    }
+    return KCT_OK;
+}
+
+bool misaligned(const void *p) { return ((uintptr_t)p & 15u) != 0; }
+
+template <typename T> kct_dtype dtype_of();
+template <> kct_dtype dtype_of<float>() { return KCT_F32; }
+template <> kct_dtype dtype_of<bf16>() { return KCT_BF16; }
+template <> kct_dtype dtype_of<_Float16>() { return KCT_F16; }
+
+#define KCT_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            set_error(std::string(fn) + ": " #expr " failed: " + hipGetErrorString(e_));         \
+            return KCT_ERR_HIP;                                                                  \
+        }                                                                                        \
+    } while (0)
+
+__global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *history)
+{
+    if (threadIdx.x != 0) return;
+    Scalars s;
+    memset(&s, 0, sizeof(s));
+    s.maxiter = maxiter;
+    s.err = err;
+    s.history = history;
+    *sc = s;
+}
+
+template <typename T>
+kct_status project_t(const Geometry *g, const void *x, void *b, void *ws, hipStream_t st)
+{
+    const char *fn = "kct_project";
+    const T *vol = (const T *)x;
+    T *vt = nullptr;
+    if (ws) {
+        vt = (T *)ws;
+        KCT_TRY(launch_transpose_xy<T>(g->dev, vol, vt, st));
+    }
+    KCT_TRY(launch_forward<T>(g->dev, vol, vt, (T *)b, nullptr, FWD_PLAIN, nullptr, nullptr, nullptr, st));
+    return KCT_OK;
+}
+
+template <typename T>
+kct_status backproject_t(const Geometry *g, const void *b, void *x, hipStream_t st)
+{
+    const char *fn = "kct_backproject";
+    KCT_TRY(launch_backward<T>(g->dev, (const T *)b, (T *)x, nullptr, BWD_PLAIN, nullptr, nullptr, nullptr, st));
+    return KCT_OK;
+}
+
+template <typename T>
+kct_status read_info(Scalars *sc, kct_solve_info *info, hipStream_t st, const char *fn, int solver)
+{
+    Scalars h;
+    KCT_TRY(hipMemcpyAsync(&h, sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    KCT_TRY(hipStreamSynchronize(st));
+    if (info) {
+        info->iterations = h.iters;
+        info->nb0 = h.nb0;
+        info->nb = h.nb;
+        info->nr2 = solver == KCT_SOLVER_CGLS ? h.nr2_old : h.nr2_now;
+        info->stop_reason = h.done ? h.stop : KCT_STOP_MAXITER;
+    }
+    if (h.done && h.stop == KCT_STOP_NUMERIC) {
+        set_error(std::string(fn) + ": a solver norm became NaN or Inf");
+        return KCT_ERR_NUMERIC;
+    }
+    return KCT_OK;
+}
+
+// CGLS with delayed residual computation (Algorithm 1).
+template <typename T>
+kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_opts *o, void *ws,
+                  kct_solve_info *info, hipStream_t st)
+{
+    const char *fn = "kct_cgls_solve";
+    const SolverLayout L = solver_layout(g, dtype_of<T>(), KCT_SOLVER_CGLS);
+    char *w = (char *)ws;
+    Scalars *sc = (Scalars *)(w + L.scal);
+    double *part = (double *)(w + L.part);
+    T *d = (T *)(w + L.v0), *dt = (T *)(w + L.v1), *r = (T *)(w + L.v2);
+    T *e = (T *)(w + L.p0), *p = (T *)(w + L.p1);
+    const T *b = (const T *)bv;
+    T *x = (T *)xv;
+    const GeoDev &G = g->dev;
+    const int64_t n = nvox(g), m = nrays(g);
+    const int64_t nf = forward_num_blocks(G), nbk = backward_num_blocks(G), ns = stream_num_blocks();
+    const int K = o->max_iter;
+    const int *done = &sc->done;
+
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history);
+    KCT_TRY(hipGetLastError());
+    // NB0 = |b|
+    KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
+    KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
+    // x = x0; p = A x; e = b - p
+    if (o->x0_is_zero) {
+        KCT_TRY(launch_fill_zero<T>(x, n, st));
+        KCT_TRY(launch_copy<T>(b, e, m, st));
+    } else {
+        KCT_TRY(launch_transpose_xy<T>(G, x, dt, st));
+        KCT_TRY(launch_forward<T>(G, x, dt, e, b, FWD_BMINUS, sc, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, nf, F_NB_INIT, st));
+    }
+    // r = A^T e; d = r; NR2_old = |r|^2
+    KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
+    KCT_TRY(launch_finalize(sc, part, nbk, F_NR2_INIT, st));
+    KCT_TRY(launch_cgls_d<T>(G, r, d, dt, sc, 1, st));
+    // p = A d; NP2 = |p|^2; alpha = NR2_old / NP2
+    KCT_TRY(launch_forward<T>(G, d, dt, p, nullptr, FWD_NORM, sc, part, done, st));
+    KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
+    // x = x + alpha d; e = e - alpha p; NB = |e|; i = 1
+    KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
+    KCT_TRY(launch_cgls_e<T>(e, p, sc, m, part, st));
+    KCT_TRY(launch_finalize(sc, part, ns, F_NB, st));
+    for (int it = 1; it < K; ++it) {
+        // r = A^T e; NR2_now = |r|^2; beta = NR2_now / NR2_old; NR2_old = NR2_now
+        KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, nbk, F_BETA, st));
+        // d = r + beta d
+        KCT_TRY(launch_cgls_d<T>(G, r, d, dt, sc, 0, st));
+        // p = A d; NP2; alpha
+        KCT_TRY(launch_forward<T>(G, d, dt, p, nullptr, FWD_NORM, sc, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
+        // x += alpha d; e -= alpha p; NB; i = i + 1 (and the while test)
+        KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
+        KCT_TRY(launch_cgls_e<T>(e, p, sc, m, part, st));
+        KCT_TRY(launch_finalize(sc, part, ns, F_NB, st));
+    }
+    return read_info<T>(sc, info, st, fn, KCT_SOLVER_CGLS);
+}
+
+// LSQR (Paige & Saunders) with the normalisations of u and v folded into the
+// fused epilogues: u = u_hat / beta and v = v_hat / alpha are never formed.
+template <typename T>
+kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_opts *o, void *ws,
+                  kct_solve_info *info, hipStream_t st)
+{
+    const char *fn = "kct_lsqr_solve";
+    const SolverLayout L = solver_layout(g, dtype_of<T>(), KCT_SOLVER_LSQR);
+    char *wp = (char *)ws;
+    Scalars *sc = (Scalars *)(wp + L.scal);
+    double *part = (double *)(wp + L.part);
+    T *v = (T *)(wp + L.v0), *vt = (T *)(wp + L.v1), *w = (T *)(wp + L.v2);
+    T *u = (T *)(wp + L.p0);
+    const T *b = (const T *)bv;
+    T *x = (T *)xv;
+    const GeoDev &G = g->dev;
+    const int64_t n = nvox(g), m = nrays(g);
+    const int64_t nf = forward_num_blocks(G), nbk = backward_num_blocks(G), ns = stream_num_blocks();
+    const int K = o->max_iter;
+    const int *done = &sc->done;
+
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history);
+    KCT_TRY(hipGetLastError());
+    KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
+    KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
+    // beta u = b - A x0
+    if (o->x0_is_zero) {
+        KCT_TRY(launch_fill_zero<T>(x, n, st));
+        KCT_TRY(launch_copy<T>(b, u, m, st));
+        KCT_TRY(launch_norm2<T>(u, m, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, ns, F_L_BETA0, st));
+    } else {
+        KCT_TRY(launch_transpose_xy<T>(G, x, vt, st));
+        KCT_TRY(launch_forward<T>(G, x, vt, u, b, FWD_BMINUS, sc, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA0, st));
+    }
+    // alpha v = A^T u; w = v
+    KCT_TRY(launch_backward<T>(G, u, v, vt, BWD_LSQR0, sc, part, done, st));
+    KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA0, st));
+    KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 1, n, st));
+    for (int it = 0; it < K; ++it) {
+        // beta u = A v - alpha u
+        KCT_TRY(launch_forward<T>(G, v, vt, u, nullptr, FWD_LSQR, sc, part, done, st));
+        KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA, st));
+        // alpha v = A^T u - beta v (skipped on the last iteration), Givens rotation
+        KCT_TRY(launch_backward<T>(G, u, v, vt, BWD_LSQR, sc, part, &sc->skip_bwd, st));
+        KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA, st));
+        // x += (phi / rho) w; w = v - (theta / rho) w
+        KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 0, n, st));
+        KCT_TRY(launch_finalize(sc, part, 0, F_L_GIVENS, st));
+    }
+    return read_info<T>(sc, info, st, fn, KCT_SOLVER_LSQR);
+}
+
+kct_status check_solve_args(kct_geometry h, kct_dtype t, const void *b, void *x, const kct_solve_opts *o, void *ws,
+                            size_t ws_bytes, int solver, const char *fn)
+{
+    kct_status s = check_geometry(h, fn);
+    if (s != KCT_OK) return s;
+    if ((s = check_dtype(t, fn)) != KCT_OK) return s;
+    if (!b || !x || !o) {
+        set_error(std::string(fn) + ": b, x and opts must not be NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (misaligned(b) || misaligned(x) || misaligned(ws)) {
+        set_error(std::string(fn) + ": buffers must be 16-byte aligned");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (o->max_iter < 0 || !(o->err_tol >= 0.0) || !std::isfinite(o->err_tol)) {
+        set_error(std::string(fn) + ": max_iter must be >= 0 and err_tol finite and >= 0");
+        return KCT_ERR_INVALID_ARG;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    size_t need = solver_layout(g, t, solver).total;
+    if (!ws || ws_bytes < need) {
+        set_error(std::string(fn) + ": workspace of " + std::to_string(ws_bytes) + " bytes, need " +
+                  std::to_string(need));
+        return KCT_ERR_WORKSPACE;
+    }
+    return KCT_OK;
+}
+
+}  // namespace
+}  // namespace kct
+
+using namespace kct;
+
+extern "C" {
+
+kct_status kct_geometry_create(const kct_volume_desc *vol, const kct_cone_desc *cone, kct_geometry *out)
+{
+    if (!vol || !cone || !out) {
+        set_error("kct_geometry_create: NULL argument");
+        return KCT_ERR_INVALID_ARG;
+    }
+    *out = nullptr;
+    Geometry *g = new (std::nothrow) Geometry();
+    if (!g) {
+        set_error("kct_geometry_create: out of host memory");
+        return KCT_ERR_INVALID_ARG;
+    }
+    kct_status s = geometry_build(*vol, *cone, g);
+    if (s != KCT_OK) {
+        delete g;
+        return s;
+    }
+    *out = reinterpret_cast<kct_geometry>(g);
+    return KCT_OK;
+}
+
+void kct_geometry_destroy(kct_geometry h)
+{
+    if (!h) return;
+    Geometry *g = reinterpret_cast<Geometry *>(h);
+    if (g->d_tables) (void)hipFree(g->d_tables);
+    delete g;
+}
+
+kct_status kct_geometry_dims(kct_geometry h, int64_t *n_vox, int64_t *n_rays)
+{
+    if (!h) {
+        set_error("kct_geometry_dims: geometry is NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    if (n_vox) *n_vox = nvox(g);
+    if (n_rays) *n_rays = nrays(g);
+    return KCT_OK;
+}
+
+kct_status kct_project_workspace_size(kct_geometry h, kct_dtype t, size_t *bytes)
+{
+    if (!h || !bytes) {
+        set_error("kct_project_workspace_size: NULL argument");
+        return KCT_ERR_INVALID_ARG;
+    }
+    kct_status s = check_dtype(t, "kct_project_workspace_size");
+    if (s != KCT_OK) return s;
+    *bytes = (size_t)nvox(reinterpret_cast<const Geometry *>(h)) * elem_size(t);
+    return KCT_OK;
+}
+
+kct_status kct_project(kct_geometry h, kct_dtype t, const void *x, void *b, void *ws, size_t ws_bytes,
+                       hipStream_t stream)
+{
+    const char *fn = "kct_project";
+    kct_status s = check_geometry(h, fn);
+    if (s != KCT_OK) return s;
+    if ((s = check_dtype(t, fn)) != KCT_OK) return s;
+    if (!x || !b) {
+        set_error("kct_project: x and b must not be NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (misaligned(x) || misaligned(b) || misaligned(ws)) {
+        set_error("kct_project: buffers must be 16-byte aligned");
+        return KCT_ERR_INVALID_ARG;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    if (ws && ws_bytes < (size_t)nvox(g) * elem_size(t)) {
+        set_error("kct_project: workspace smaller than kct_project_workspace_size");
+        return KCT_ERR_WORKSPACE;
+    }
+    switch (t) {
+    case KCT_F32: return project_t<float>(g, x, b, ws, stream);
+    case KCT_BF16: return project_t<bf16>(g, x, b, ws, stream);
+    default: return project_t<_Float16>(g, x, b, ws, stream);
+    }
+}
+
+kct_status kct_backproject(kct_geometry h, kct_dtype t, const void *b, void *x, hipStream_t stream)
+{
+    const char *fn = "kct_backproject";
+    kct_status s = check_geometry(h, fn);
+    if (s != KCT_OK) return s;
+    if ((s = check_dtype(t, fn)) != KCT_OK) return s;
+    if (!x || !b) {
+        set_error("kct_backproject: b and x must not be NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (misaligned(x) || misaligned(b)) {
+        set_error("kct_backproject: buffers must be 16-byte aligned");
+        return KCT_ERR_INVALID_ARG;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    switch (t) {
+    case KCT_F32: return backproject_t<float>(g, b, x, stream);
+    case KCT_BF16: return backproject_t<bf16>(g, b, x, stream);
+    default: return backproject_t<_Float16>(g, b, x, stream);
+    }
+}
+
+kct_status kct_solver_workspace_size(kct_geometry h, kct_dtype t, int32_t solver, size_t *bytes)
+{
+    if (!h || !bytes) {
+        set_error("kct_solver_workspace_size: NULL argument");
+        return KCT_ERR_INVALID_ARG;
+    }
+    kct_status s = check_dtype(t, "kct_solver_workspace_size");
+    if (s != KCT_OK) return s;
+    if (solver != KCT_SOLVER_CGLS && solver != KCT_SOLVER_LSQR) {
+        set_error("kct_solver_workspace_size: unknown solver");
+        return KCT_ERR_INVALID_ARG;
+    }
+    *bytes = solver_layout(reinterpret_cast<const Geometry *>(h), t, solver).total;
+    return KCT_OK;
+}
+
+kct_status kct_cgls_solve(kct_geometry h, kct_dtype t, const void *b, void *x, const kct_solve_opts *opts, void *ws,
+                          size_t ws_bytes, kct_solve_info *info, hipStream_t stream)
+{
+    kct_status s = check_solve_args(h, t, b, x, opts, ws, ws_bytes, KCT_SOLVER_CGLS, "kct_cgls_solve");
+    if (s != KCT_OK) return s;
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    switch (t) {
+    case KCT_F32: return cgls_t<float>(g, b, x, opts, ws, info, stream);
+    case KCT_BF16: return cgls_t<bf16>(g, b, x, opts, ws, info, stream);
+    default: return cgls_t<_Float16>(g, b, x, opts, ws, info, stream);
+    }
+}
+
+kct_status kct_lsqr_solve(kct_geometry h, kct_dtype t, const void *b, void *x, const kct_solve_opts *opts, void *ws,
+                          size_t ws_bytes, kct_solve_info *info, hipStream_t stream)
+{
+    kct_status s = check_solve_args(h, t, b, x, opts, ws, ws_bytes, KCT_SOLVER_LSQR, "kct_lsqr_solve");
+    if (s != KCT_OK) return s;
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    switch (t) {
+    case KCT_F32: return lsqr_t<float>(g, b, x, opts, ws, info, stream);
+    case KCT_BF16: return lsqr_t<bf16>(g, b, x, opts, ws, info, stream);
+    default: return lsqr_t<_Float16>(g, b, x, opts, ws, info, stream);
+    }
+}
+
+const char *kct_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

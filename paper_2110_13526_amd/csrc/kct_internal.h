@@ -1,0 +1,164 @@
+// kct_internal.h -- types shared by the host side and the kernels of the
+// cone-beam projector library (not part of the public C ABI).
+//
+// The geometry is reduced on the host, in double precision, to per-view,
+// per-detector-column and per-detector-row parameters of the rays, rounded once
+// to single precision.  Every kernel that needs the weight w_ij of a ray and a
+// voxel reads these same numbers and evaluates the same inline functions
+// (kct_weights.h), which is what makes the backprojector the exact transpose of
+// the forward projector.
+//
+// Ray parametrisation.  For each view one in-plane axis is "dominant" (x when
+// |cos t| / vx >= |sin t| / vy, else y); call it xi and the other in-plane axis
+// eta.  Coordinates are voxel-index units centred on the volume centre, so the
+// voxel planes along an axis with n cells sit at m - n/2, m = 0..n.  A ray of
+// detector column iu and row iv is then
+//     eta(xi)  = eta_c + a * xi                       (column parameters)
+//     zeta(xi) = zeta_c + xi / czr,  zeta_c = qz * tcv - zc,  czr = inv_qz * kz
+// and its length in mm per unit of xi is L = sqrt(lxy2 + (qz * gp)^2).
+// The ray crosses eta-plane mb (centred) at xi = (mb - eta_c) * inv_a and
+// zeta-plane mb at xi = (mb - zeta_c) * czr.  Parametrising by the centred
+// index along the dominant axis keeps every quantity O(volume size), so single
+// precision resolves a crossing to about 1e-5 of a voxel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kct.h"
+
+namespace kct {
+
+struct ColParam {    // per (view, detector column)
+    float eta_c;     // eta (centred index) where the ray meets the plane xi = 0
+    float inv_a;     // d xi / d eta; 0 when the ray is parallel to the eta planes
+    float a;         // d eta / d xi
+    float tcv;       // (fraction of the source->pixel segment at xi = 0) / vz
+    float kz;        // vz * (xi extent of the segment in mm) / vxi
+    float gp;        // fraction of the source->pixel segment per unit of xi
+    float lxy2;      // in-plane part of (mm per unit xi)^2
+    float pad;
+};
+
+struct RowParam {    // per detector row
+    float qz;        // z of the pixel centre [mm] (the source is at z = 0)
+    float inv_qz;    // 1 / qz, 0 when qz == 0
+};
+
+struct ViewParam {   // per view
+    float sx, sy;    // source position [mm]
+    float c, s;      // cos and sin of the view angle
+    int dom;         // 0: xi = x, eta = y;  1: xi = y, eta = x
+    int pad[3];
+};
+
+// Everything the kernels need, passed by value.
+struct GeoDev {
+    int nx, ny, nz, nviews, nu, nv;
+    float vx, vy, vz;
+    float x0, y0, z0;        // world coordinates of the volume's lower corner [mm]
+    float hx, hy, hz;        // nx/2, ny/2, nz/2
+    float zc;                // cz / vz
+    float inv_vz;
+    float sdd, du, dv, off_u, off_v;
+    float cu, cv;            // (nu - 1)/2, (nv - 1)/2
+    const ColParam *cols;    // [nviews][nu]
+    const RowParam *rows;    // [nv]
+    const ViewParam *views;  // [nviews]
+};
+
+// Double-precision solver state kept on the device (one per solve).
+struct Scalars {
+    // CGLS (Algorithm 1)
+    double nb0, nb, nr2_old, nr2_now, np2, alpha, beta;
+    // LSQR (Paige & Saunders)
+    double l_alpha, l_beta, rhobar, phibar, rho, phi, theta, cg, sg;
+    double fwd_c1, fwd_c2;   // u_hat' = c1 * (A v_hat) - c2 * u_hat
+    double bwd_c1, bwd_c2;   // v_hat' = c1 * (A^T u_hat) - c2 * v_hat
+    double x_coef, w_coef, w_vcoef;  // x += x_coef w;  w = w_vcoef v_hat - w_coef w
+    double err;
+    double *history;
+    int iters, done, stop, maxiter;
+    int skip_bwd, pad0, pad1, pad2;
+};
+
+enum FinalizeOp {
+    F_NB0 = 0,
+    F_NB_INIT,
+    F_NR2_INIT,
+    F_ALPHA,
+    F_NB,
+    F_BETA,
+    F_L_BETA0,
+    F_L_ALPHA0,
+    F_L_BETA,
+    F_L_ALPHA,
+    F_L_GIVENS,
+};
+
+// Forward-projection epilogues.
+enum FwdEpi {
+    FWD_PLAIN = 0,  // out = A x
+    FWD_NORM,       // out = A x, partial |out|^2
+    FWD_BMINUS,     // out = aux - A x, partial |out|^2
+    FWD_LSQR,       // out = c1 * A x - c2 * out, partial |out|^2 (reads scalars)
+};
+
+// Backprojection epilogues.
+enum BwdEpi {
+    BWD_PLAIN = 0,  // out = A^T y
+    BWD_NORM,       // out = A^T y, partial |out|^2
+    BWD_LSQR0,      // out = c1 * A^T y, also transposed copy, partial |out|^2
+    BWD_LSQR,       // out = c1 * A^T y - c2 * out, also transposed copy, partial |out|^2
+};
+
+struct Geometry {
+    kct_volume_desc vol;
+    kct_cone_desc cone;
+    int device;
+    GeoDev dev;
+    void *d_tables;  // one allocation holding cols, rows and views
+    size_t table_bytes;
+};
+
+// bfloat16 storage: the upper 16 bits of an IEEE single (raw bits).
+struct bf16 {
+    uint16_t bits;
+};
+
+// Kernel launchers (defined in the .hip files).
+template <typename T>
+hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_t, T *out, const T *aux, int epi,
+                          const Scalars *sc, double *partials, const int *skip, hipStream_t st);
+template <typename T>
+hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_t, int epi, const Scalars *sc,
+                           double *partials, const int *skip, hipStream_t st);
+int64_t forward_num_blocks(const GeoDev &g);
+int64_t backward_num_blocks(const GeoDev &g);
+
+// Vector kernels (kernels_vec.hip).
+int64_t stream_num_blocks();
+template <typename T>
+hipError_t launch_transpose_xy(const GeoDev &g, const T *src, T *dst, hipStream_t st);
+template <typename T>
+hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip, hipStream_t st);
+hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st);
+template <typename T>
+hipError_t launch_fill_zero(T *v, int64_t n, hipStream_t st);
+template <typename T>
+hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
+// x += alpha d
+template <typename T>
+hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st);
+// d = r (+ beta d) and its transposed copy
+template <typename T>
+hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dt, const Scalars *sc, int first,
+                         hipStream_t st);
+// e -= alpha p, partial |e|^2
+template <typename T>
+hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double *partials, hipStream_t st);
+// LSQR: w = w_vcoef v (init) or x += x_coef w; w = w_vcoef v - w_coef w
+template <typename T>
+hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st);
+
+}  // namespace kct

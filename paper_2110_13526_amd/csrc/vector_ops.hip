@@ -1,0 +1,385 @@
+// vector_ops.hip -- the streaming vector updates and the double-precision
+// scalar steps of CGLS (Section 2, Algorithm 1) and LSQR on gfx950.
+//
+// Reductions are deterministic: every producing kernel writes one partial sum
+// per workgroup, and a one-workgroup finalize kernel adds the partials in a
+// fixed order and performs the scalar algebra (norms, alpha, beta, Givens
+// rotation, stop tests) in double precision on the device.  No atomics.
+//
+// Kernels on the iteration path take a pointer to the solver's "done" flag and
+// return at once when it is set, so a solve can be enqueued in full without
+// host synchronisation and still stop early (tolerance reached, breakdown).
+#include "kct_internal.h"
+#include "kct_weights.h"
+
+namespace kct {
+
+constexpr int STREAM_BLOCKS = 2048;  // grid of the streaming kernels (8 per CU)
+constexpr int TB = 256;
+
+int64_t stream_num_blocks() { return STREAM_BLOCKS; }
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[TB / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    return r;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TB) void k_norm2(const T *__restrict__ v, int64_t n, double *__restrict__ partials,
+                                              const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        double x = (double)to_f32(v[i]);
+        s += x * x;
+    }
+    double b = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(TB) void k_fill_zero(T *__restrict__ v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
+        v[i] = from_f32<T>(0.0f);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TB) void k_copy(const T *__restrict__ s, T *__restrict__ d, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) d[i] = s[i];
+}
+
+// x += alpha d
+template <typename T>
+__global__ __launch_bounds__(TB) void k_cgls_x(T *__restrict__ x, const T *__restrict__ d,
+                                               const Scalars *__restrict__ sc, int64_t n)
+{
+    if (sc->done) return;
+    const float alpha = (float)sc->alpha;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
+        x[i] = from_f32<T>(to_f32(x[i]) + alpha * to_f32(d[i]));
+}
+
+// e -= alpha p, partial |e|^2
+template <typename T>
+__global__ __launch_bounds__(TB) void k_cgls_e(T *__restrict__ e, const T *__restrict__ p,
+                                               const Scalars *__restrict__ sc, int64_t n,
+                                               double *__restrict__ partials)
+{
+    if (sc->done) return;
+    const float alpha = (float)sc->alpha;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        const T v = from_f32<T>(to_f32(e[i]) - alpha * to_f32(p[i]));
+        e[i] = v;
+        const double dv = (double)to_f32(v);
+        s += dv * dv;
+    }
+    double b = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = b;
+}
+
+// d = r + beta d (first: d = r), and dt = d with x and y swapped, through a
+// 32 x 32 LDS tile so that both the plain and the transposed stores coalesce.
+template <typename T, int FIRST>
+__global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, const T *__restrict__ r, T *__restrict__ d,
+                                               T *__restrict__ dt, const Scalars *__restrict__ sc)
+{
+    if (sc->done) return;
+    __shared__ float tile[32][33];
+    const float beta = FIRST ? 0.0f : (float)sc->beta;
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const size_t zoff = (size_t)blockIdx.z * nx * ny;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    for (int j = ty; j < 32; j += 8) {
+        const int x = bx + tx, y = by + j;
+        if (x < nx && y < ny) {
+            const size_t i = zoff + (size_t)y * nx + x;
+            float v = to_f32(r[i]);
+            if (!FIRST) v = v + beta * to_f32(d[i]);
+            const T st = from_f32<T>(v);
+            d[i] = st;
+            tile[j][tx] = to_f32(st);
+        }
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int y = by + tx, x = bx + j;
+        if (x < nx && y < ny) dt[zoff + (size_t)x * ny + y] = from_f32<T>(tile[tx][j]);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TB) void k_transpose_xy(int nx, int ny, const T *__restrict__ s, T *__restrict__ dt)
+{
+    __shared__ T tile[32][33];
+    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const size_t zoff = (size_t)blockIdx.z * nx * ny;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int j = ty; j < 32; j += 8) {
+        const int x = bx + tx, y = by + j;
+        if (x < nx && y < ny) tile[j][tx] = s[zoff + (size_t)y * nx + x];
+    }
+    __syncthreads();
+    for (int j = ty; j < 32; j += 8) {
+        const int y = by + tx, x = bx + j;
+        if (x < nx && y < ny) dt[zoff + (size_t)x * ny + y] = tile[tx][j];
+    }
+}
+
+// LSQR: init: w = w_vcoef v.  Iteration: x += x_coef w; w = w_vcoef v - w_coef w.
+template <typename T, int INIT>
+__global__ __launch_bounds__(TB) void k_lsqr_xw(T *__restrict__ x, T *__restrict__ w, const T *__restrict__ v,
+                                                const Scalars *__restrict__ sc, int64_t n)
+{
+    if (sc->done) return;
+    const float vc = (float)sc->w_vcoef;
+    if (INIT) {
+        for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
+            w[i] = from_f32<T>(vc * to_f32(v[i]));
+        return;
+    }
+    const float xc = (float)sc->x_coef, wc = (float)sc->w_coef;
+    const bool upd_w = sc->w_vcoef != 0.0 || sc->w_coef != 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
+        const float wi = to_f32(w[i]);
+        x[i] = from_f32<T>(to_f32(x[i]) + xc * wi);
+        if (upd_w) w[i] = from_f32<T>(vc * to_f32(v[i]) - wc * wi);
+    }
+}
+
+// Fixed-order sum of the partials followed by one scalar step.
+__global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const double *__restrict__ partials,
+                                                 int64_t np, int op)
+{
+    if (op != F_NB0 && sc->done) return;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < np; i += TB) s += partials[i];
+    __shared__ double red[TB];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double S = red[0];
+    auto stop = [&](int reason) {
+        sc->done = 1;
+        sc->stop = reason;
+        sc->skip_bwd = 1;
+    };
+    switch (op) {
+    case F_NB0:  // NB0 = |b|
+        sc->nb0 = sqrt(S);
+        sc->nb = sc->nb0;
+        sc->phibar = sc->nb0;
+        if (sc->maxiter <= 0) stop(KCT_STOP_MAXITER);
+        break;
+    case F_NB_INIT:  // NB of e = b - A x0 (reported if the first step breaks down)
+        sc->nb = sqrt(S);
+        if (!isfinite(sc->nb)) stop(KCT_STOP_NUMERIC);
+        break;
+    case F_NR2_INIT:  // NR2_old = |r|^2
+        sc->nr2_old = S;
+        sc->nr2_now = S;
+        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
+        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
+        break;
+    case F_ALPHA:  // NP2 = |p|^2, alpha = NR2_old / NP2
+        sc->np2 = S;
+        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
+        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
+        else sc->alpha = sc->nr2_old / S;
+        break;
+    case F_NB: {  // NB = |e|, i = i + 1, stop test of the while loop
+        const double nb = sqrt(S);
+        sc->nb = nb;
+        sc->iters += 1;
+        if (sc->history) sc->history[sc->iters - 1] = sc->nb0 > 0.0 ? nb / sc->nb0 : 0.0;
+        if (!isfinite(nb)) stop(KCT_STOP_NUMERIC);
+        else if (!(nb > sc->err * sc->nb0)) stop(sc->iters >= sc->maxiter ? KCT_STOP_MAXITER : KCT_STOP_TOL);
+        else if (sc->iters >= sc->maxiter) stop(KCT_STOP_MAXITER);
+        break;
+    }
+    case F_BETA:  // NR2_now = |r|^2, beta = NR2_now / NR2_old, NR2_old = NR2_now
+        sc->nr2_now = S;
+        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
+        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
+        else {
+            sc->beta = S / sc->nr2_old;
+            sc->nr2_old = S;
+        }
+        break;
+    case F_L_BETA0: {  // beta_1 = |u_hat|, u = u_hat / beta_1
+        const double b = sqrt(S);
+        sc->l_beta = b;
+        sc->phibar = b;
+        sc->nb = b;
+        if (!isfinite(b)) stop(KCT_STOP_NUMERIC);
+        else if (b == 0.0) stop(KCT_STOP_BREAKDOWN);
+        else { sc->bwd_c1 = 1.0 / b; sc->bwd_c2 = 0.0; }
+        break;
+    }
+    case F_L_ALPHA0: {  // alpha_1 = |v_hat|, w_1 = v_hat / alpha_1
+        const double a = sqrt(S);
+        sc->l_alpha = a;
+        sc->rhobar = a;
+        sc->nr2_now = S;
+        if (!isfinite(a)) stop(KCT_STOP_NUMERIC);
+        else if (a == 0.0) stop(KCT_STOP_BREAKDOWN);
+        else {
+            sc->w_vcoef = 1.0 / a;
+            sc->fwd_c1 = 1.0 / a;
+            sc->fwd_c2 = a / sc->l_beta;
+        }
+        break;
+    }
+    case F_L_BETA: {  // beta_{i+1} = |A v - alpha u| (u_hat' already formed by the forward epilogue)
+        const double b = sqrt(S);
+        sc->l_beta = b;
+        if (!isfinite(b)) { stop(KCT_STOP_NUMERIC); break; }
+        // the backprojection of this iteration is skipped on the last iteration
+        // and when beta = 0 (then the rotation ends the solve anyway)
+        sc->skip_bwd = (b == 0.0 || sc->iters + 1 >= sc->maxiter) ? 1 : 0;
+        if (b != 0.0) { sc->bwd_c1 = 1.0 / b; sc->bwd_c2 = b / sc->l_alpha; }
+        break;
+    }
+    case F_L_ALPHA: {  // alpha_{i+1} = |A^T u - beta v| (0 when the backprojection was skipped)
+        const double a = sc->skip_bwd ? 0.0 : sqrt(S);
+        sc->nr2_now = a * a;
+        if (!isfinite(a)) { stop(KCT_STOP_NUMERIC); break; }
+        // Givens rotation (Paige & Saunders)
+        const double beta = sc->l_beta;
+        const double rho = sqrt(sc->rhobar * sc->rhobar + beta * beta);
+        const double c = sc->rhobar / rho, s = beta / rho;
+        const double theta = s * a;
+        sc->rho = rho;
+        sc->cg = c;
+        sc->sg = s;
+        sc->theta = theta;
+        sc->rhobar = -c * a;
+        sc->phi = c * sc->phibar;
+        sc->phibar = s * sc->phibar;
+        sc->x_coef = sc->phi / rho;
+        sc->w_coef = theta / rho;
+        sc->w_vcoef = a != 0.0 ? 1.0 / a : 0.0;
+        if (a == 0.0) sc->w_coef = 0.0;
+        sc->l_alpha = a;
+        if (a != 0.0) { sc->fwd_c1 = 1.0 / a; sc->fwd_c2 = a / beta; }
+        break;
+    }
+    case F_L_GIVENS: {  // after x and w are updated: i = i + 1, stop tests
+        sc->iters += 1;
+        const double nb = fabs(sc->phibar);
+        sc->nb = nb;
+        if (sc->history) sc->history[sc->iters - 1] = sc->nb0 > 0.0 ? nb / sc->nb0 : 0.0;
+        if (!isfinite(nb)) stop(KCT_STOP_NUMERIC);
+        else if (sc->l_beta == 0.0 || (sc->iters < sc->maxiter && sc->l_alpha == 0.0)) stop(KCT_STOP_BREAKDOWN);
+        else if (!(nb > sc->err * sc->nb0)) stop(sc->iters >= sc->maxiter ? KCT_STOP_MAXITER : KCT_STOP_TOL);
+        else if (sc->iters >= sc->maxiter) stop(KCT_STOP_MAXITER);
+        break;
+    }
+    default:
+        break;
+    }
+}
+
+static dim3 sgrid(int64_t n)
+{
+    int64_t b = (n + TB - 1) / TB;
+    if (b > STREAM_BLOCKS) b = STREAM_BLOCKS;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+template <typename T>
+hipError_t launch_transpose_xy(const GeoDev &g, const T *src, T *dst, hipStream_t st)
+{
+    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
+    hipLaunchKernelGGL(k_transpose_xy<T>, grid, dim3(TB), 0, st, g.nx, g.ny, src, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip, hipStream_t st)
+{
+    // always STREAM_BLOCKS partials so the finalize step reads a fixed count
+    hipLaunchKernelGGL(k_norm2<T>, dim3(STREAM_BLOCKS), dim3(TB), 0, st, v, n, partials, skip);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TB), 0, st, sc, partials, nparts, op);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_zero(T *v, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_zero<T>, sgrid(n), dim3(TB), 0, st, v, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy<T>, sgrid(n), dim3(TB), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgls_x<T>, sgrid(n), dim3(TB), 0, st, x, d, sc, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dt, const Scalars *sc, int first, hipStream_t st)
+{
+    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
+    if (first) hipLaunchKernelGGL((k_cgls_d<T, 1>), grid, dim3(TB), 0, st, g.nx, g.ny, r, d, dt, sc);
+    else hipLaunchKernelGGL((k_cgls_d<T, 0>), grid, dim3(TB), 0, st, g.nx, g.ny, r, d, dt, sc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_cgls_e<T>, dim3(STREAM_BLOCKS), dim3(TB), 0, st, e, p, sc, n, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st)
+{
+    if (init) hipLaunchKernelGGL((k_lsqr_xw<T, 1>), sgrid(n), dim3(TB), 0, st, x, w, v, sc, n);
+    else hipLaunchKernelGGL((k_lsqr_xw<T, 0>), sgrid(n), dim3(TB), 0, st, x, w, v, sc, n);
+    return hipGetLastError();
+}
+
+#define KCT_VINST(T)                                                                                       \
+    template hipError_t launch_transpose_xy<T>(const GeoDev &, const T *, T *, hipStream_t);              \
+    template hipError_t launch_norm2<T>(const T *, int64_t, double *, const int *, hipStream_t);          \
+    template hipError_t launch_fill_zero<T>(T *, int64_t, hipStream_t);                                   \
+    template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                             \
+    template hipError_t launch_cgls_x<T>(T *, const T *, const Scalars *, int64_t, hipStream_t);          \
+    template hipError_t launch_cgls_d<T>(const GeoDev &, const T *, T *, T *, const Scalars *, int,       \
+                                         hipStream_t);                                                    \
+    template hipError_t launch_cgls_e<T>(T *, const T *, const Scalars *, int64_t, double *, hipStream_t); \
+    template hipError_t launch_lsqr_xw<T>(T *, T *, const T *, const Scalars *, int, int64_t, hipStream_t);
+KCT_VINST(float)
+KCT_VINST(bf16)
+KCT_VINST(_Float16)
+
+}  // namespace kct

@@ -1,0 +1,79 @@
+"""CPU-side checks of the C ABI library and the package (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+import kct_inputs as ki
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kct.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kct_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2110_13526_amd import _lib
+    L = ctypes.CDLL(_lib.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), f"libkct.so does not export {n}"
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_binding_loads_the_library():
+    from paper_2110_13526_amd import _lib
+    L = _lib.load()
+    assert L.kct_last_error() == b""
+
+
+def test_product_does_not_use_the_oracle():
+    """Neither the package nor its HIP sources name the oracle."""
+    pkg = os.path.join(ROOT, "paper_2110_13526_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "kct_oracle" not in text and "libkct_oracle" not in text, f
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the C structs have the sizes of their C definitions (x86-64 ABI)."""
+    from paper_2110_13526_amd import _lib
+    assert ctypes.sizeof(_lib.VolumeDesc) == 3 * 4 + 4 + 6 * 8
+    assert ctypes.sizeof(_lib.ConeDesc) == 4 + 4 + 2 * 8 + 8 + 2 * 8 + 2 * 4 + 4 * 8
+    assert ctypes.sizeof(_lib.SolveOpts) == 4 + 4 + 8 + 4 + 4 + 8
+    assert ctypes.sizeof(_lib.SolveInfo) == 4 + 4 + 3 * 8 + 4 + 4
+
+
+def test_phantom_recipe():
+    g = ki.config("c1")
+    e = ki.draw_ellipsoids(g, 10, 101)
+    assert len(e) == 10 and e[0].density == 1.0
+    L = g.side_mm()
+    for el in e[1:]:
+        assert np.all(np.abs(el.centre) <= 0.35 * L)
+        assert np.all((el.semi >= 4.0 * L / 64) & (el.semi <= 28.0 * L / 64))
+        assert -0.8 <= el.density <= 1.0
+        assert np.allclose(el.rot @ el.rot.T, np.eye(3), atol=1e-12)
+    x1 = ki.phantom(g, 10, 101)
+    x2 = ki.phantom(g, 10, 101)
+    assert np.array_equal(x1, x2) and x1.shape == g.vol_shape
+
+
+def test_noise_models():
+    b = np.linspace(0.0, 100.0, 100000).astype(np.float64)
+    n = ki.gaussian_noise(b, 0.005, 1)
+    assert abs(np.std(n - b) - 0.5) < 0.02
+    p = ki.poisson_log_noise(b, 1e4, 2)
+    # log-transformed counts: unbiased to first order, variance 1 / (c^2 I) per ray
+    c = 4.0 / 100.0
+    mid = slice(40000, 60000)
+    expect = 1.0 / (c * c * 1e4 * np.exp(-c * b[mid]))
+    assert abs(np.var(p[mid] - b[mid]) / np.mean(expect) - 1.0) < 0.1

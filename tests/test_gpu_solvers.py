@@ -1,0 +1,138 @@
+"""GPU CGLS (Algorithm 1) and LSQR against the FP64 oracle, through the C ABI.
+
+Tolerance after K iterations: relative L2 1e-4 for x_K and for the discrepancy
+history (single-precision vectors, double-precision scalars on the device).
+"""
+import numpy as np
+import pytest
+
+import kct_inputs as ki
+import oracle
+from tests.gpu_util import dev, geometry, rel, say, to_dev, to_np, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def c1_problem():
+    """64^3, 90 views, 96 x 96 detector (truncated), 10-ellipsoid phantom, 0.5 % Gaussian noise."""
+    g = ki.config("c1")
+    say("[solvers] c1 problem")
+    x_true = ki.phantom(g, ki.N_ELLIPSOIDS["c1"], ki.SEEDS["c1"])
+    b = oracle.project(g, x_true.astype(np.float64))
+    b = ki.gaussian_noise(b, 0.005, ki.SEEDS["c1"] + 1_000_000).astype(np.float32)
+    return g, geometry(g), x_true, b
+
+
+def test_cgls_c1_matches_oracle(c1_problem):
+    import paper_2110_13526_amd as kct
+    g, G, x_true, b = c1_problem
+    K = 10
+    ref = oracle.cgls(g, b.astype(np.float64), K)
+    x, info = kct.cgls(G, to_dev(b), K, history=True)
+    say(f"[solvers] cgls c1: it={info.iterations} nb={info.nb} ref nb={ref.nb}")
+    assert info.iterations == ref.iterations == K
+    assert info.stop_reason == kct.STOP_MAXITER
+    assert rel(to_np(x), ref.x) < TOL, rel(to_np(x), ref.x)
+    np.testing.assert_allclose(to_np(info.history), ref.history, rtol=TOL)
+    assert abs(info.nb0 - ref.nb0) <= 1e-6 * ref.nb0
+    assert abs(info.nb - ref.nb) <= TOL * ref.nb
+
+
+def test_lsqr_c1_matches_oracle(c1_problem):
+    import paper_2110_13526_amd as kct
+    g, G, x_true, b = c1_problem
+    K = 10
+    ref = oracle.lsqr(g, b.astype(np.float64), K)
+    x, info = kct.lsqr(G, to_dev(b), K, history=True)
+    assert info.iterations == ref.iterations == K
+    assert rel(to_np(x), ref.x) < TOL, rel(to_np(x), ref.x)
+    np.testing.assert_allclose(to_np(info.history), ref.history, rtol=TOL)
+
+
+def test_cgls_warm_start_and_tolerance(c1_problem):
+    """x0 != 0 (Section 3: initial guess) and the ERR stop of Algorithm 1."""
+    import paper_2110_13526_amd as kct
+    g, G, x_true, b = c1_problem
+    x0 = (0.5 * x_true).astype(np.float32)
+    ref = oracle.cgls(g, b.astype(np.float64), 6, x0=x0.astype(np.float64))
+    x, info = kct.cgls(G, to_dev(b), 6, x0=to_dev(x0))
+    assert info.iterations == 6
+    assert rel(to_np(x), ref.x) < TOL
+    ref = oracle.cgls(g, b.astype(np.float64), 50, err=0.05)
+    x, info = kct.cgls(G, to_dev(b), 50, err=0.05, history=True)
+    assert ref.stop_reason == oracle.STOP_TOL and info.stop_reason == kct.STOP_TOL
+    assert info.iterations == ref.iterations
+    assert rel(to_np(x), ref.x) < TOL
+    refl = oracle.lsqr(g, b.astype(np.float64), 6, x0=x0.astype(np.float64))
+    xl, infol = kct.lsqr(G, to_dev(b), 6, x0=to_dev(x0))
+    assert rel(to_np(xl), refl.x) < TOL
+
+
+def test_solver_edge_cases(c1_problem):
+    """b = 0 breaks down at once with x = 0; K = 0 returns x0."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g, G, x_true, b = c1_problem
+    zero = torch.zeros(g.proj_shape, dtype=torch.float32, device=dev())
+    for solve in (kct.cgls, kct.lsqr):
+        x, info = solve(G, zero, 5)
+        assert info.iterations == 0 and info.stop_reason == kct.STOP_BREAKDOWN
+        assert not torch.any(x)
+        x0 = to_dev(x_true)
+        x, info = solve(G, to_dev(b), 0, x0=x0)
+        assert info.iterations == 0 and torch.equal(x, x0)
+
+
+def test_cgls_deterministic(c1_problem):
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g, G, x_true, b = c1_problem
+    bd = to_dev(b)
+    x1, _ = kct.cgls(G, bd, 5)
+    x2, _ = kct.cgls(G, bd, 5)
+    assert torch.equal(x1, x2)
+
+
+def test_cgls_c2_properties():
+    """256^3 / 360 views / 384^2, Poisson-log noise, 40 iterations (too large for the
+    oracle to iterate): properties that hold at any size -- discrepancy history
+    non-increasing, LSQR practically identical to CGLS, updated discrepancy equal to
+    the recomputed |b - A x_K| (the paper reports < 0.0001 % after 10 iterations) --
+    and the first iterate against its closed form x_1 = alpha r_0 evaluated with the
+    oracle on sampled voxels."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g = ki.config("c2")
+    say("[solvers] c2 problem")
+    x_true = ki.phantom(g, ki.N_ELLIPSOIDS["c2"], ki.SEEDS["c2"])
+    G = geometry(g)
+    b_clean = kct.project(G, to_dev(x_true))
+    b = to_dev(ki.poisson_log_noise(to_np(b_clean).astype(np.float32), 1e4, ki.SEEDS["c2"] + 1_000_000))
+    del b_clean
+    K = 40
+    x, info = kct.cgls(G, b, K, history=True)
+    h = to_np(info.history)
+    say(f"[solvers] c2 cgls: it={info.iterations} e={h[-1]:.5f}")
+    assert info.iterations == K
+    assert np.all(np.diff(h) <= 1e-6 * h[:-1])
+    recomputed = torch.linalg.vector_norm((b - kct.project(G, x)).double()).item()
+    assert abs(recomputed - info.nb) / recomputed < 1e-3
+    xl, infol = kct.lsqr(G, b, K, history=True)
+    hl = to_np(infol.history)
+    np.testing.assert_allclose(hl, h, rtol=1e-2)
+    assert rel(to_np(xl), to_np(x)) < 2e-2
+    # x_1 = alpha r_0 with r_0 = A^T b, alpha = |r_0|^2 / |A r_0|^2, checked on sampled voxels
+    x1, info1 = kct.cgls(G, b, 1)
+    r0 = kct.backproject(G, b)
+    ar0 = kct.project(G, r0)
+    alpha = (torch.linalg.vector_norm(r0.double()) ** 2 / torch.linalg.vector_norm(ar0.double()) ** 2).item()
+    rng = np.random.default_rng(5)
+    vox = rng.choice(g.n_vox, 200, replace=False)
+    ref_r0 = oracle.backproject_voxels(g, to_np(b), vox)
+    got = to_np(x1.view(-1)[torch.from_numpy(vox).to(dev())])
+    assert rel(got, alpha * ref_r0) < TOL
+    del x, xl, x1, r0, ar0, b
+    torch.cuda.empty_cache()
