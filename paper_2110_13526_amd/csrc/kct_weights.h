@@ -49,19 +49,27 @@ __host__ __device__ __forceinline__ float ray_length_per_xi(float lxy2, float qz
 __host__ __device__ __forceinline__ int parallel_cell(float c, float half_n) { return (int)floorf(c + half_n); }
 
 // xi-range [lo, hi] of cell m of an axis with n cells (half_n = n/2), for a ray
-// whose coordinate on that axis is c + xi / inv (inv == 0: parallel).
-__host__ __device__ __forceinline__ void cell_range(int m, float half_n, float c, float inv, float &lo, float &hi)
+// whose coordinate on that axis is c + xi / inv (inv == 0: parallel).  mb must
+// be the cell's lower plane, (float)m - half_n (exact), passed in so callers
+// that walk consecutive cells need not recompute it.
+__host__ __device__ __forceinline__ void cell_range_mb(int m, float mb, float half_n, float c, float inv, float &lo,
+                                                       float &hi)
 {
     if (inv == 0.0f) {
         bool in = (m == parallel_cell(c, half_n));
         lo = in ? -INFINITY : INFINITY;
         hi = INFINITY;
     } else {
-        float b0 = cross_at((float)m - half_n, c, inv);
-        float b1 = cross_at((float)(m + 1) - half_n, c, inv);
+        float b0 = cross_at(mb, c, inv);
+        float b1 = cross_at(mb + 1.0f, c, inv);
         lo = fminf(b0, b1);
         hi = fmaxf(b0, b1);
     }
+}
+
+__host__ __device__ __forceinline__ void cell_range(int m, float half_n, float c, float inv, float &lo, float &hi)
+{
+    cell_range_mb(m, (float)m - half_n, half_n, c, inv, lo, hi);
 }
 
 // ---------------------------------------------------------------- storage

@@ -1,4 +1,4 @@
-// projector.hip -- the cone-beam projector pair for gfx950.
+// projector.hip -- the forward cone-beam projector for gfx950.
 //
 //   forward  p = A x    (Section 2, Eq. 1): ray-driven.  One lane per ray; the
 //            64 lanes of a wavefront are 64 neighbouring detector columns of one
@@ -8,14 +8,11 @@
 //            merging the crossings of the three families of voxel planes
 //            (Siddon's traversal), and accumulates w_ij * x_j in single
 //            precision.
-//   backward r = A^T e  (Section 2, Eq. 2): voxel-driven gather.  One lane per
-//            voxel; for every view the lane enumerates the detector pixels whose
-//            rays can meet its voxel and evaluates the same weight as the
-//            forward kernel.  Every output is written exactly once: no atomics,
-//            bitwise reproducible.
+// The backprojector (the voxel-driven gather that evaluates the same weights)
+// is in backproject.hip.
 //
-// Both kernels can fuse a double-precision partial sum of the squares of their
-// outputs (|p|^2, |r|^2 of Algorithm 1) and the LSQR bidiagonalisation update.
+// The kernel can fuse a double-precision partial sum of the squares of its
+// outputs (|p|^2 of Algorithm 1) and the LSQR bidiagonalisation update.
 #include "kct_internal.h"
 #include "kct_ray.h"
 #include "kct_weights.h"
@@ -24,7 +21,6 @@ namespace kct {
 
 constexpr int FWD_COLS = 64;  // detector columns per workgroup (one wavefront)
 constexpr int FWD_ROWS = 4;   // detector rows per workgroup (one per wavefront)
-constexpr int BWD_TX = 16, BWD_TY = 16;
 
 // Sum of v over the 256 threads of the workgroup, in a fixed order.  Result is
 // valid in thread 0.
@@ -96,48 +92,9 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
     }
 }
 
-template <typename T, int EPI>
-__global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
-                                                  T *__restrict__ out_t, const Scalars *__restrict__ sc,
-                                                  double *__restrict__ partials, const int *__restrict__ skip)
-{
-    if (skip && *skip) return;
-    const int ix = blockIdx.x * BWD_TX + (threadIdx.x % BWD_TX);
-    const int iy = blockIdx.y * BWD_TY + (threadIdx.x / BWD_TX);
-    const int iz = blockIdx.z;
-    const bool valid = ix < g.nx && iy < g.ny;
-    float acc = 0.0f;
-    if (valid) {
-        acc = gather_voxel<T>(g, proj, ix, iy, iz);
-    }
-    const size_t vox = ((size_t)iz * g.ny + iy) * g.nx + ix;
-    double sq = 0.0;
-    if (valid) {
-        float o;
-        if (EPI == BWD_LSQR0) o = (float)sc->bwd_c1 * acc;
-        else if (EPI == BWD_LSQR) o = (float)sc->bwd_c1 * acc - (float)sc->bwd_c2 * to_f32(out[vox]);
-        else o = acc;
-        const T st = from_f32<T>(o);
-        out[vox] = st;
-        if (EPI == BWD_LSQR0 || EPI == BWD_LSQR) out_t[((size_t)iz * g.nx + ix) * g.ny + iy] = st;
-        const double od = (double)to_f32(st);
-        sq = od * od;
-    }
-    if (EPI != BWD_PLAIN) {
-        const double bs = block_sum_256(sq);
-        if (threadIdx.x == 0)
-            partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = bs;
-    }
-}
-
 int64_t forward_num_blocks(const GeoDev &g)
 {
     return (int64_t)((g.nu + FWD_COLS - 1) / FWD_COLS) * ((g.nv + FWD_ROWS - 1) / FWD_ROWS) * g.nviews;
-}
-
-int64_t backward_num_blocks(const GeoDev &g)
-{
-    return (int64_t)((g.nx + BWD_TX - 1) / BWD_TX) * ((g.ny + BWD_TY - 1) / BWD_TY) * g.nz;
 }
 
 template <typename T>
@@ -166,36 +123,9 @@ hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_t, T *out,
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_t, int epi, const Scalars *sc,
-                           double *partials, const int *skip, hipStream_t st)
-{
-    dim3 grid((g.nx + BWD_TX - 1) / BWD_TX, (g.ny + BWD_TY - 1) / BWD_TY, g.nz);
-    dim3 block(256);
-    switch (epi) {
-    case BWD_PLAIN:
-        hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip);
-        break;
-    case BWD_NORM:
-        hipLaunchKernelGGL((k_backward<T, BWD_NORM>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip);
-        break;
-    case BWD_LSQR0:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR0>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip);
-        break;
-    case BWD_LSQR:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 #define KCT_INST(T)                                                                                              \
     template hipError_t launch_forward<T>(const GeoDev &, const T *, const T *, T *, const T *, int,            \
-                                          const Scalars *, double *, const int *, hipStream_t);                 \
-    template hipError_t launch_backward<T>(const GeoDev &, const T *, T *, T *, int, const Scalars *, double *,  \
-                                           const int *, hipStream_t);
+                                          const Scalars *, double *, const int *, hipStream_t);
 KCT_INST(float)
 KCT_INST(bf16)
 KCT_INST(_Float16)
