@@ -29,7 +29,7 @@ __device__ __forceinline__ double bwd_block_sum(double v)
 
 template <typename T, int EPI>
 __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
-                                                  T *__restrict__ out_t, const Scalars *__restrict__ sc,
+                                                  T *__restrict__ out_z, const Scalars *__restrict__ sc,
                                                   double *__restrict__ partials, const int *__restrict__ skip, int nbx,
                                                   int nby, int nbz)
 {
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict_
             else o = acc[j];
             const T st = from_f32<T>(o);
             out[vox] = st;
-            if (EPI == BWD_LSQR0 || EPI == BWD_LSQR) out_t[((size_t)iz * g.nx + ix) * g.ny + iy] = st;
+            if (EPI == BWD_LSQR0 || EPI == BWD_LSQR) out_z[((size_t)iy * g.nx + ix) * g.nz + iz] = st;
             const double od = (double)to_f32(st);
             sq += od * od;
         }
@@ -165,7 +165,7 @@ int64_t backward_num_blocks(const GeoDev &g)
 }
 
 template <typename T>
-hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_t, int epi, const Scalars *sc,
+hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
                            double *partials, const int *skip, hipStream_t st)
 {
     int nbx, nby, nbz;
@@ -174,19 +174,19 @@ hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_t, int
     dim3 block(256);
     switch (epi) {
     case BWD_PLAIN:
-        hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip,
+        hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
                            nbx, nby, nbz);
         break;
     case BWD_NORM:
-        hipLaunchKernelGGL((k_backward<T, BWD_NORM>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip,
+        hipLaunchKernelGGL((k_backward<T, BWD_NORM>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
                            nbx, nby, nbz);
         break;
     case BWD_LSQR0:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR0>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip,
+        hipLaunchKernelGGL((k_backward<T, BWD_LSQR0>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
                            nbx, nby, nbz);
         break;
     case BWD_LSQR:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR>), grid, block, 0, st, g, proj, out, out_t, sc, partials, skip,
+        hipLaunchKernelGGL((k_backward<T, BWD_LSQR>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
                            nbx, nby, nbz);
         break;
     default:

@@ -121,12 +121,12 @@ kct_status project_t(const Geometry *g, const void *x, void *b, void *ws, hipStr
 {
     const char *fn = "kct_project";
     const T *vol = (const T *)x;
-    T *vt = nullptr;
+    T *vz = nullptr;
     if (ws) {
-        vt = (T *)ws;
-        KCT_TRY(launch_transpose_xy<T>(g->dev, vol, vt, st));
+        vz = (T *)ws;
+        KCT_TRY(launch_zfast_copy<T>(g->dev, vol, vz, st));
     }
-    KCT_TRY(launch_forward<T>(g->dev, vol, vt, (T *)b, nullptr, FWD_PLAIN, nullptr, nullptr, nullptr, st));
+    KCT_TRY(launch_forward<T>(g->dev, vol, vz, (T *)b, nullptr, FWD_PLAIN, nullptr, nullptr, nullptr, st));
     return KCT_OK;
 }
 
@@ -168,7 +168,7 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     char *w = (char *)ws;
     Scalars *sc = (Scalars *)(w + L.scal);
     double *part = (double *)(w + L.part);
-    T *d = (T *)(w + L.v0), *dt = (T *)(w + L.v1), *r = (T *)(w + L.v2);
+    T *d = (T *)(w + L.v0), *dz = (T *)(w + L.v1), *r = (T *)(w + L.v2);
     T *e = (T *)(w + L.p0), *p = (T *)(w + L.p1);
     const T *b = (const T *)bv;
     T *x = (T *)xv;
@@ -188,16 +188,16 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         KCT_TRY(launch_fill_zero<T>(x, n, st));
         KCT_TRY(launch_copy<T>(b, e, m, st));
     } else {
-        KCT_TRY(launch_transpose_xy<T>(G, x, dt, st));
-        KCT_TRY(launch_forward<T>(G, x, dt, e, b, FWD_BMINUS, sc, part, done, st));
+        KCT_TRY(launch_zfast_copy<T>(G, x, dz, st));
+        KCT_TRY(launch_forward<T>(G, x, dz, e, b, FWD_BMINUS, sc, part, done, st));
         KCT_TRY(launch_finalize(sc, part, nf, F_NB_INIT, st));
     }
     // r = A^T e; d = r; NR2_old = |r|^2
     KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
     KCT_TRY(launch_finalize(sc, part, nbk, F_NR2_INIT, st));
-    KCT_TRY(launch_cgls_d<T>(G, r, d, dt, sc, 1, st));
+    KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 1, st));
     // p = A d; NP2 = |p|^2; alpha = NR2_old / NP2
-    KCT_TRY(launch_forward<T>(G, d, dt, p, nullptr, FWD_NORM, sc, part, done, st));
+    KCT_TRY(launch_forward<T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st));
     KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
     // x = x + alpha d; e = e - alpha p; NB = |e|; i = 1
     KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
@@ -208,9 +208,9 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
         KCT_TRY(launch_finalize(sc, part, nbk, F_BETA, st));
         // d = r + beta d
-        KCT_TRY(launch_cgls_d<T>(G, r, d, dt, sc, 0, st));
+        KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 0, st));
         // p = A d; NP2; alpha
-        KCT_TRY(launch_forward<T>(G, d, dt, p, nullptr, FWD_NORM, sc, part, done, st));
+        KCT_TRY(launch_forward<T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st));
         KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
         // x += alpha d; e -= alpha p; NB; i = i + 1 (and the while test)
         KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
@@ -231,7 +231,7 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     char *wp = (char *)ws;
     Scalars *sc = (Scalars *)(wp + L.scal);
     double *part = (double *)(wp + L.part);
-    T *v = (T *)(wp + L.v0), *vt = (T *)(wp + L.v1), *w = (T *)(wp + L.v2);
+    T *v = (T *)(wp + L.v0), *vz = (T *)(wp + L.v1), *w = (T *)(wp + L.v2);
     T *u = (T *)(wp + L.p0);
     const T *b = (const T *)bv;
     T *x = (T *)xv;
@@ -252,20 +252,20 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         KCT_TRY(launch_norm2<T>(u, m, part, done, st));
         KCT_TRY(launch_finalize(sc, part, ns, F_L_BETA0, st));
     } else {
-        KCT_TRY(launch_transpose_xy<T>(G, x, vt, st));
-        KCT_TRY(launch_forward<T>(G, x, vt, u, b, FWD_BMINUS, sc, part, done, st));
+        KCT_TRY(launch_zfast_copy<T>(G, x, vz, st));
+        KCT_TRY(launch_forward<T>(G, x, vz, u, b, FWD_BMINUS, sc, part, done, st));
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA0, st));
     }
     // alpha v = A^T u; w = v
-    KCT_TRY(launch_backward<T>(G, u, v, vt, BWD_LSQR0, sc, part, done, st));
+    KCT_TRY(launch_backward<T>(G, u, v, vz, BWD_LSQR0, sc, part, done, st));
     KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA0, st));
     KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 1, n, st));
     for (int it = 0; it < K; ++it) {
         // beta u = A v - alpha u
-        KCT_TRY(launch_forward<T>(G, v, vt, u, nullptr, FWD_LSQR, sc, part, done, st));
+        KCT_TRY(launch_forward<T>(G, v, vz, u, nullptr, FWD_LSQR, sc, part, done, st));
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA, st));
         // alpha v = A^T u - beta v (skipped on the last iteration), Givens rotation
-        KCT_TRY(launch_backward<T>(G, u, v, vt, BWD_LSQR, sc, part, &sc->skip_bwd, st));
+        KCT_TRY(launch_backward<T>(G, u, v, vz, BWD_LSQR, sc, part, &sc->skip_bwd, st));
         KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA, st));
         // x += (phi / rho) w; w = v - (theta / rho) w
         KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 0, n, st));

@@ -108,8 +108,8 @@ enum FwdEpi {
 enum BwdEpi {
     BWD_PLAIN = 0,  // out = A^T y
     BWD_NORM,       // out = A^T y, partial |out|^2
-    BWD_LSQR0,      // out = c1 * A^T y, also transposed copy, partial |out|^2
-    BWD_LSQR,       // out = c1 * A^T y - c2 * out, also transposed copy, partial |out|^2
+    BWD_LSQR0,      // out = c1 * A^T y, also z-fastest copy, partial |out|^2
+    BWD_LSQR,       // out = c1 * A^T y - c2 * out, also z-fastest copy, partial |out|^2
 };
 
 struct Geometry {
@@ -128,18 +128,21 @@ struct bf16 {
 
 // Kernel launchers (defined in the .hip files).
 template <typename T>
-hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_t, T *out, const T *aux, int epi,
+hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_z, T *out, const T *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st);
+// vol_z (optional): the same volume stored z-fastest, vol_z[(iy * nx + ix) * nz + iz].
+// out_z (LSQR epilogues only): receives the output in that layout as well.
 template <typename T>
-hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_t, int epi, const Scalars *sc,
+hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
                            double *partials, const int *skip, hipStream_t st);
 int64_t forward_num_blocks(const GeoDev &g);
 int64_t backward_num_blocks(const GeoDev &g);
 
-// Vector kernels (kernels_vec.hip).
+// Vector kernels (vector_ops.hip).
 int64_t stream_num_blocks();
+// dst[(iy * nx + ix) * nz + iz] = src[(iz * ny + iy) * nx + ix]
 template <typename T>
-hipError_t launch_transpose_xy(const GeoDev &g, const T *src, T *dst, hipStream_t st);
+hipError_t launch_zfast_copy(const GeoDev &g, const T *src, T *dst, hipStream_t st);
 template <typename T>
 hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip, hipStream_t st);
 hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st);
@@ -150,9 +153,9 @@ hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
 // x += alpha d
 template <typename T>
 hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st);
-// d = r (+ beta d) and its transposed copy
+// d = r (+ beta d) and its z-fastest copy
 template <typename T>
-hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dt, const Scalars *sc, int first,
+hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first,
                          hipStream_t st);
 // e -= alpha p, partial |e|^2
 template <typename T>

@@ -1,5 +1,5 @@
 // kct_ray.h -- the forward projector's walk along one ray (Siddon's merge of
-// the three families of voxel-plane crossings).  It evaluates the weight
+// the three families of voxel-plane crossings, in increasing xi).  It evaluates the weight
 // function of kct_weights.h, as the backprojector's gather (kct_gather.h) does,
 // on the same table entries, so both see identical weights.  Host-callable as
 // well, so the kernel arithmetic can be run on a CPU.
@@ -13,108 +13,132 @@
 namespace kct {
 
 // Walk one ray through the volume and return sum_j (xi-length in voxel j) * x_j.
-// base/sxi/seta/szeta address the volume as [zeta][xi][eta].
+//
+// The walk is split so that a wavefront whose lanes are rays of one detector
+// column (different rows) does identical in-plane work in every lane:
+//   * the in-plane walk (xi and eta planes) depends on the column only; it
+//     enumerates the pieces [t0, t1] of the ray's shadow in the (x, y) plane,
+//     one per in-plane cell, in increasing xi;
+//   * the zeta walk is per lane: inside each in-plane piece the lane adds the
+//     piece's part in its current z-cell and steps to the next z-cell when the
+//     ray crosses a z-plane before t1 (rare: z-slopes are small).
+// Every weight is min(the three highs) - max(the three lows) of kct_weights.h:
+// t0 equals the larger in-plane low (the walk starts at an exact cell and t0 is
+// always the crossing at which the current in-plane cell was entered).
+// Volume addressing: element (zeta cell m, xi cell i, eta cell e) is at
+// vol[m * sz + i * sxi + e * seta].  With the z-fastest copy of the volume
+// (sz = 1) the 64 lanes of a wavefront read neighbouring addresses.
+// z-cells -1 and nz stand for "below" and "above" the volume: nothing is read
+// there, and the crossing out of the volume is never followed back.
 template <typename T>
-__host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ base, int sxi, int seta, int szeta, int nxi,
-                                           int neta, int nz, float hxi, float heta, float hz, float eta_c,
-                                           float inv_a, float a, float zeta_c, float czr)
+__host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ vol, int sxi, int seta, int sz, int nxi,
+                                                    int neta, int nz, float hxi, float heta, float hz, float eta_c,
+                                                    float inv_a, float a, float zeta_c, float czr)
 {
-    // Parameter interval of the ray inside the volume box.
-    float lo_e, hi_e, lo_z, hi_z;
+    // In-plane extent [t_start, t_end] of the ray inside the volume's (x, y) box.
+    float lo_e, hi_e;
     if (inv_a == 0.0f) {
-        int m = parallel_cell(eta_c, heta);
-        bool in = m >= 0 && m < neta;
+        const int m = parallel_cell(eta_c, heta);
+        const bool in = m >= 0 && m < neta;
         lo_e = in ? -INFINITY : INFINITY;
         hi_e = in ? INFINITY : -INFINITY;
     } else {
-        float b0 = cross_at(-heta, eta_c, inv_a), b1 = cross_at(heta, eta_c, inv_a);
+        const float b0 = cross_at(-heta, eta_c, inv_a), b1 = cross_at(heta, eta_c, inv_a);
         lo_e = fminf(b0, b1);
         hi_e = fmaxf(b0, b1);
     }
+    const float t_start = fmaxf(-hxi, lo_e);
+    const float t_end = fminf(hxi, hi_e);
+    if (!(t_end > t_start)) return 0.0f;
+    // This lane's extent in z; a ray that never meets the volume does nothing.
     if (czr == 0.0f) {
-        int m = parallel_cell(zeta_c, hz);
-        bool in = m >= 0 && m < nz;
-        lo_z = in ? -INFINITY : INFINITY;
-        hi_z = in ? INFINITY : -INFINITY;
+        const int m = parallel_cell(zeta_c, hz);
+        if (m < 0 || m >= nz) return 0.0f;
     } else {
-        float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at(hz, zeta_c, czr);
-        lo_z = fminf(b0, b1);
-        hi_z = fmaxf(b0, b1);
+        const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at(hz, zeta_c, czr);
+        if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) return 0.0f;
     }
-    const float entry = fmaxf(-hxi, fmaxf(lo_e, lo_z));
-    const float exit_ = fminf(hxi, fminf(hi_e, hi_z));
-    if (!(exit_ > entry)) return 0.0f;
 
-    // Start every axis at its entry cell or one cell earlier along the ray
-    // (clamped into the volume).  An earlier cell ends at or before the entry
-    // point, so it receives a zero length and the walk moves on.
-    int mx = (int)floorf(entry + hxi) - 1;
+    // Exact in-plane cells at t_start: lo <= t_start < hi on both axes.
+    int mx = (int)floorf(t_start + hxi);
     mx = mx < 0 ? 0 : (mx > nxi - 1 ? nxi - 1 : mx);
-    float lx = (float)mx - hxi;
-    float hx = lx + 1.0f;
-
+    float hx = (float)(mx + 1) - hxi;
+    while (hx <= t_start && mx < nxi - 1) { ++mx; hx += 1.0f; }
+    while (hx - 1.0f > t_start && mx > 0) { --mx; hx -= 1.0f; }
     int me, ste;
-    float le, he, mbe;
+    float he, mbe;
     if (inv_a == 0.0f) {
         me = parallel_cell(eta_c, heta);
         ste = 0;
-        le = -INFINITY;
         he = INFINITY;
         mbe = 0.0f;
     } else {
         ste = inv_a > 0.0f ? 1 : -1;
-        int m = (int)floorf(eta_c + a * entry + heta) - ste;
+        int m = (int)floorf(eta_c + a * t_start + heta);
         me = m < 0 ? 0 : (m > neta - 1 ? neta - 1 : m);
-        float mb_lo = (float)(ste > 0 ? me : me + 1) - heta;
-        mbe = (float)(ste > 0 ? me + 1 : me) - heta;
-        le = cross_at(mb_lo, eta_c, inv_a);
+        mbe = (float)(ste > 0 ? me + 1 : me) - heta;  // plane of the cell's exit crossing
         he = cross_at(mbe, eta_c, inv_a);
+        float le = cross_at(mbe - (float)ste, eta_c, inv_a);
+        while (he <= t_start && me + ste >= 0 && me + ste < neta) {
+            me += ste;
+            mbe += (float)ste;
+            le = he;
+            he = cross_at(mbe, eta_c, inv_a);
+        }
+        while (le > t_start && me - ste >= 0 && me - ste < neta) {
+            me -= ste;
+            mbe -= (float)ste;
+            he = le;
+            le = cross_at(mbe - (float)ste, eta_c, inv_a);
+        }
     }
-    int mz, stz;
-    float lz, hzv, mbz;
+
+    // z state: start at the cell of t_start or one before it along the ray
+    // (clamped to the sentinels -1 / nz); the first piece then moves on.
+    int mz, stz, hb;
+    float lz, hzv;
     if (czr == 0.0f) {
         mz = parallel_cell(zeta_c, hz);
         stz = 0;
+        hb = 0;
         lz = -INFINITY;
         hzv = INFINITY;
-        mbz = 0.0f;
     } else {
         stz = czr > 0.0f ? 1 : -1;
-        int m = (int)floorf(zeta_c + entry / czr + hz) - stz;
-        mz = m < 0 ? 0 : (m > nz - 1 ? nz - 1 : m);
-        float mb_lo = (float)(stz > 0 ? mz : mz + 1) - hz;
-        mbz = (float)(stz > 0 ? mz + 1 : mz) - hz;
-        lz = cross_at(mb_lo, zeta_c, czr);
-        hzv = cross_at(mbz, zeta_c, czr);
+        int m = (int)floorf(zeta_c + t_start / czr + hz) - stz;
+        mz = m < -1 ? -1 : (m > nz ? nz : m);
+        hb = stz > 0 ? mz + 1 : mz;
+        const int lb = hb - stz;
+        lz = (lb >= 0 && lb <= nz) ? cross_at((float)lb - hz, zeta_c, czr) : -INFINITY;
+        hzv = (hb >= 0 && hb <= nz) ? cross_at((float)hb - hz, zeta_c, czr) : INFINITY;
     }
 
-    int idx = mz * szeta + mx * sxi + me * seta;
-    const int de = ste * seta, dz = stz * szeta;
-    const float fste = (float)ste, fstz = (float)stz;
+    int base = mx * sxi + me * seta;
+    const int de = ste * seta;
+    const float fste = (float)ste;
     float acc = 0.0f;
-    const int maxit = nxi + neta + nz + 8;
-    for (int it = 0; it < maxit; ++it) {
-        const float lmax = fmaxf(lx, fmaxf(le, lz));
-        if (!(lmax < exit_)) break;
-        const float hmin = fminf(hx, fminf(he, hzv));
-        const float w = fmaxf(hmin - lmax, 0.0f);
-        acc = __builtin_fmaf(w, to_f32(base[idx]), acc);
-        const bool ax = hx == hmin, ae = he == hmin, az = hzv == hmin;
-        lx = ax ? hx : lx;
-        hx = ax ? hx + 1.0f : hx;
-        idx += ax ? sxi : 0;
-        const float mbe_n = mbe + fste;
-        const float he_n = cross_at(mbe_n, eta_c, inv_a);
-        le = ae ? he : le;
-        mbe = ae ? mbe_n : mbe;
-        he = ae ? he_n : he;
-        idx += ae ? de : 0;
-        const float mbz_n = mbz + fstz;
-        const float hz_n = cross_at(mbz_n, zeta_c, czr);
-        lz = az ? hzv : lz;
-        mbz = az ? mbz_n : mbz;
-        hzv = az ? hz_n : hzv;
-        idx += az ? dz : 0;
+    float t0 = t_start;
+    for (int guard = nxi + neta + 4; t0 < t_end && guard > 0; --guard) {
+        const float t1 = fminf(hx, he);
+        for (int zg = nz + 2; zg > 0; --zg) {
+            const float w = fminf(t1, hzv) - fmaxf(t0, lz);
+            if (w > 0.0f && (unsigned)mz < (unsigned)nz) acc = __builtin_fmaf(w, to_f32(vol[base + mz * sz]), acc);
+            if (!(hzv < t1)) break;
+            lz = hzv;
+            mz += stz;
+            hb += stz;
+            hzv = (hb >= 0 && hb <= nz) ? cross_at((float)hb - hz, zeta_c, czr) : INFINITY;
+        }
+        if (hx == t1) {
+            hx += 1.0f;
+            base += sxi;
+        }
+        if (he == t1) {
+            mbe += fste;
+            he = cross_at(mbe, eta_c, inv_a);
+            base += de;
+        }
+        t0 = t1;
     }
     return acc;
 }

@@ -1,13 +1,12 @@
 // projector.hip -- the forward cone-beam projector for gfx950.
 //
 //   forward  p = A x    (Section 2, Eq. 1): ray-driven.  One lane per ray; the
-//            64 lanes of a wavefront are 64 neighbouring detector columns of one
-//            row, so their voxel reads fall on neighbouring addresses when the
-//            volume is stored with the eta axis (the non-dominant in-plane axis)
-//            fastest.  Each lane walks the voxels of its ray in increasing xi,
-//            merging the crossings of the three families of voxel planes
-//            (Siddon's traversal), and accumulates w_ij * x_j in single
-//            precision.
+//            64 lanes of a wavefront are 64 neighbouring detector rows of one
+//            column.  Their rays share the in-plane part of the walk (identical
+//            work in every lane, no divergence), differ only in z, and read a
+//            copy of the volume stored z-fastest, so one gather instruction of
+//            the wavefront touches a few neighbouring cache lines.  Each lane
+//            accumulates w_ij * x_j in single precision (kct_ray.h).
 // The backprojector (the voxel-driven gather that evaluates the same weights)
 // is in backproject.hip.
 //
@@ -19,8 +18,9 @@
 
 namespace kct {
 
-constexpr int FWD_COLS = 64;  // detector columns per workgroup (one wavefront)
-constexpr int FWD_ROWS = 4;   // detector rows per workgroup (one per wavefront)
+constexpr int FWD_COLS = 4;    // detector columns per workgroup (one per wavefront)
+constexpr int FWD_ROWS = 64;   // detector rows per wavefront (one per lane)
+constexpr int NXCD = 8;
 
 // Sum of v over the 256 threads of the workgroup, in a fixed order.  Result is
 // valid in thread 0.
@@ -36,30 +36,57 @@ __device__ __forceinline__ double block_sum_256(double v)
     return r;
 }
 
+struct FwdGrid {
+    int ncg, nbands, nviews;
+    int64_t nblocks;
+};
+
+__host__ __device__ __forceinline__ FwdGrid fwd_grid(const GeoDev &g)
+{
+    FwdGrid f;
+    f.ncg = (g.nu + FWD_COLS - 1) / FWD_COLS;
+    f.nbands = (g.nv + FWD_ROWS - 1) / FWD_ROWS;
+    f.nviews = g.nviews;
+    f.nblocks = (int64_t)f.ncg * f.nbands * f.nviews;
+    return f;
+}
+
+// Workgroup order: column group fastest, then view, then row band, so the
+// workgroups in flight cover one band of detector rows (one z-slab of the
+// volume) over many views.  Dispatch fills the eight XCDs round-robin; within
+// every 64 consecutive workgroups the order is permuted so that each XCD gets 8
+// neighbouring column groups, which share voxels in that XCD's L2.
 template <typename T, int EPI>
-__global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__ vol, const T *__restrict__ vol_t,
+__global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__ vol, const T *__restrict__ vol_z,
                                                  T *__restrict__ out, const T *__restrict__ aux,
                                                  const Scalars *__restrict__ sc, double *__restrict__ partials,
                                                  const int *__restrict__ skip)
 {
     if (skip && *skip) return;
-    const int k = blockIdx.z;
-    const int iu = blockIdx.x * FWD_COLS + (threadIdx.x & 63);
-    const int iv = blockIdx.y * FWD_ROWS + (threadIdx.x >> 6);
+    const FwdGrid fg = fwd_grid(g);
+    const int64_t w = blockIdx.x;
+    const int64_t full = fg.nblocks & ~(int64_t)63;
+    const int64_t L = w < full ? (w & ~(int64_t)63) + (w % NXCD) * 8 + (w / NXCD) % 8 : w;
+    const int cg = (int)(L % fg.ncg);
+    const int64_t rest = L / fg.ncg;
+    const int k = (int)(rest % fg.nviews);
+    const int band = (int)(rest / fg.nviews);
+    const int iu = cg * FWD_COLS + (int)(threadIdx.x >> 6);
+    const int iv = band * FWD_ROWS + (int)(threadIdx.x & 63);
     const ViewParam vp = g.views[k];
     const bool valid = iu < g.nu && iv < g.nv;
 
-    const int szeta = g.nx * g.ny;
-    int nxi, neta, sxi, seta;
+    int nxi, neta, sxi, seta, sz;
     float hxi, heta;
     const T *base;
-    if (vp.dom == 0) {
+    if (vp.dom == 0) {  // xi = x, eta = y
         nxi = g.nx; neta = g.ny; hxi = g.hx; heta = g.hy;
-        if (vol_t) { base = vol_t; sxi = g.ny; seta = 1; }
-        else { base = vol; sxi = 1; seta = g.nx; }
-    } else {
+        if (vol_z) { base = vol_z; sz = 1; sxi = g.nz; seta = g.nx * g.nz; }
+        else { base = vol; sz = g.nx * g.ny; sxi = 1; seta = g.nx; }
+    } else {            // xi = y, eta = x
         nxi = g.ny; neta = g.nx; hxi = g.hy; heta = g.hx;
-        base = vol; sxi = g.nx; seta = 1;
+        if (vol_z) { base = vol_z; sz = 1; sxi = g.nx * g.nz; seta = g.nz; }
+        else { base = vol; sz = g.nx * g.ny; sxi = g.nx; seta = 1; }
     }
 
     float p = 0.0f;
@@ -69,8 +96,8 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
         const float zeta_c = zeta_centre(rp.qz, cp.tcv, g.zc);
         const float czr = zeta_inv_slope(rp.inv_qz, cp.kz);
         const float L = ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
-        const float s = trace_ray<T>(base, sxi, seta, szeta, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a,
-                                     cp.a, zeta_c, czr);
+        const float s = trace_ray<T>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a,
+                                     zeta_c, czr);
         p = L * s;
     }
     const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
@@ -87,35 +114,31 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
     }
     if (EPI != FWD_PLAIN) {
         const double bs = block_sum_256(sq);
-        if (threadIdx.x == 0)
-            partials[((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = bs;
+        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
     }
 }
 
-int64_t forward_num_blocks(const GeoDev &g)
-{
-    return (int64_t)((g.nu + FWD_COLS - 1) / FWD_COLS) * ((g.nv + FWD_ROWS - 1) / FWD_ROWS) * g.nviews;
-}
+int64_t forward_num_blocks(const GeoDev &g) { return fwd_grid(g).nblocks; }
 
 template <typename T>
-hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_t, T *out, const T *aux, int epi,
+hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_z, T *out, const T *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st)
 {
-    dim3 grid((g.nu + FWD_COLS - 1) / FWD_COLS, (g.nv + FWD_ROWS - 1) / FWD_ROWS, g.nviews);
+    dim3 grid((unsigned)fwd_grid(g).nblocks);
     dim3 block(256);
     switch (epi) {
     case FWD_PLAIN:
-        hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_t, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     case FWD_NORM:
-        hipLaunchKernelGGL((k_forward<T, FWD_NORM>), grid, block, 0, st, g, vol, vol_t, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<T, FWD_NORM>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     case FWD_BMINUS:
-        hipLaunchKernelGGL((k_forward<T, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_t, out, aux, sc, partials,
+        hipLaunchKernelGGL((k_forward<T, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
                            skip);
         break;
     case FWD_LSQR:
-        hipLaunchKernelGGL((k_forward<T, FWD_LSQR>), grid, block, 0, st, g, vol, vol_t, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<T, FWD_LSQR>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     default:
         return hipErrorInvalidValue;

@@ -87,22 +87,22 @@ __global__ __launch_bounds__(TB) void k_cgls_e(T *__restrict__ e, const T *__res
     if (threadIdx.x == 0) partials[blockIdx.x] = b;
 }
 
-// d = r + beta d (first: d = r), and dt = d with x and y swapped, through a
-// 32 x 32 LDS tile so that both the plain and the transposed stores coalesce.
+// d = r + beta d (first: d = r), and dz = d stored z-fastest.  A workgroup
+// takes a 32 (z) x 32 (x) tile of one y-plane through LDS, so the plain and
+// the z-fastest stores both coalesce.
 template <typename T, int FIRST>
-__global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, const T *__restrict__ r, T *__restrict__ d,
-                                               T *__restrict__ dt, const Scalars *__restrict__ sc)
+__global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *__restrict__ r, T *__restrict__ d,
+                                               T *__restrict__ dz, const Scalars *__restrict__ sc)
 {
     if (sc->done) return;
     __shared__ float tile[32][33];
     const float beta = FIRST ? 0.0f : (float)sc->beta;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const size_t zoff = (size_t)blockIdx.z * nx * ny;
+    const int bx = blockIdx.x * 32, bz = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int j = ty; j < 32; j += 8) {
-        const int x = bx + tx, y = by + j;
-        if (x < nx && y < ny) {
-            const size_t i = zoff + (size_t)y * nx + x;
+        const int x = bx + tx, z = bz + j;
+        if (x < nx && z < nz) {
+            const size_t i = ((size_t)z * ny + y) * nx + x;
             float v = to_f32(r[i]);
             if (!FIRST) v = v + beta * to_f32(d[i]);
             const T st = from_f32<T>(v);
@@ -112,26 +112,25 @@ __global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, const T *__restri
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
-        const int y = by + tx, x = bx + j;
-        if (x < nx && y < ny) dt[zoff + (size_t)x * ny + y] = from_f32<T>(tile[tx][j]);
+        const int z = bz + tx, x = bx + j;
+        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = from_f32<T>(tile[tx][j]);
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(TB) void k_transpose_xy(int nx, int ny, const T *__restrict__ s, T *__restrict__ dt)
+__global__ __launch_bounds__(TB) void k_zfast_copy(int nx, int ny, int nz, const T *__restrict__ s, T *__restrict__ dz)
 {
     __shared__ T tile[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
-    const size_t zoff = (size_t)blockIdx.z * nx * ny;
+    const int bx = blockIdx.x * 32, bz = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int j = ty; j < 32; j += 8) {
-        const int x = bx + tx, y = by + j;
-        if (x < nx && y < ny) tile[j][tx] = s[zoff + (size_t)y * nx + x];
+        const int x = bx + tx, z = bz + j;
+        if (x < nx && z < nz) tile[j][tx] = s[((size_t)z * ny + y) * nx + x];
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
-        const int y = by + tx, x = bx + j;
-        if (x < nx && y < ny) dt[zoff + (size_t)x * ny + y] = tile[tx][j];
+        const int z = bz + tx, x = bx + j;
+        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = tile[tx][j];
     }
 }
 
@@ -302,10 +301,10 @@ static dim3 sgrid(int64_t n)
 }
 
 template <typename T>
-hipError_t launch_transpose_xy(const GeoDev &g, const T *src, T *dst, hipStream_t st)
+hipError_t launch_zfast_copy(const GeoDev &g, const T *src, T *dst, hipStream_t st)
 {
-    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
-    hipLaunchKernelGGL(k_transpose_xy<T>, grid, dim3(TB), 0, st, g.nx, g.ny, src, dst);
+    dim3 grid((g.nx + 31) / 32, (g.nz + 31) / 32, g.ny);
+    hipLaunchKernelGGL(k_zfast_copy<T>, grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, src, dst);
     return hipGetLastError();
 }
 
@@ -345,11 +344,11 @@ hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStre
 }
 
 template <typename T>
-hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dt, const Scalars *sc, int first, hipStream_t st)
+hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first, hipStream_t st)
 {
-    dim3 grid((g.nx + 31) / 32, (g.ny + 31) / 32, g.nz);
-    if (first) hipLaunchKernelGGL((k_cgls_d<T, 1>), grid, dim3(TB), 0, st, g.nx, g.ny, r, d, dt, sc);
-    else hipLaunchKernelGGL((k_cgls_d<T, 0>), grid, dim3(TB), 0, st, g.nx, g.ny, r, d, dt, sc);
+    dim3 grid((g.nx + 31) / 32, (g.nz + 31) / 32, g.ny);
+    if (first) hipLaunchKernelGGL((k_cgls_d<T, 1>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc);
+    else hipLaunchKernelGGL((k_cgls_d<T, 0>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc);
     return hipGetLastError();
 }
 
@@ -369,7 +368,7 @@ hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, i
 }
 
 #define KCT_VINST(T)                                                                                       \
-    template hipError_t launch_transpose_xy<T>(const GeoDev &, const T *, T *, hipStream_t);              \
+    template hipError_t launch_zfast_copy<T>(const GeoDev &, const T *, T *, hipStream_t);                \
     template hipError_t launch_norm2<T>(const T *, int64_t, double *, const int *, hipStream_t);          \
     template hipError_t launch_fill_zero<T>(T *, int64_t, hipStream_t);                                   \
     template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                             \
