@@ -27,7 +27,8 @@
  * Memory layout (dense, no padding): volume x[iz][iy][ix] (ix fastest),
  * projections b[k][iv][iu] (iu fastest).  Storage type is chosen per call
  * (kct_dtype); ray and voxel accumulation is single precision, solver scalars
- * (norms, step lengths, Givens rotations) are double precision on the device.
+ * (norms, step lengths, Givens rotations) are double precision on the device,
+ * and the solvers' iterate x is always single precision.
  *
  * Conventions for every function below:
  *  - Data pointers are DEVICE pointers of the current HIP device unless marked
@@ -106,8 +107,8 @@ void kct_geometry_destroy(kct_geometry g);
 kct_status kct_geometry_dims(kct_geometry g, int64_t *n_vox, int64_t *n_rays);
 
 /* Bytes of workspace kct_project needs for its best layout: one volume in
- * the storage type (a copy with x and y swapped, read by views whose rays run
- * mostly along x). */
+ * the storage type (a copy of x stored z-fastest, which lets the rays of one
+ * detector column, held by neighbouring lanes, read neighbouring addresses). */
 kct_status kct_project_workspace_size(kct_geometry g, kct_dtype dtype, size_t *bytes);
 
 /* Forward projection b := A x (Section 2, Eq. 1; standalone projection,
@@ -146,16 +147,18 @@ typedef struct {
 
 enum { KCT_SOLVER_CGLS = 0, KCT_SOLVER_LSQR = 1 };
 
-/* Workspace bytes for a solver.  CGLS holds d, r and a transposed copy of d
+/* Workspace bytes for a solver.  CGLS holds d, r and a z-fastest copy of d
  * (volumes) and e, p (projections): the paper's three volumes and three
- * projection vectors with x and b (Section 5) plus the transposed copy, and a
- * small block of double-precision scalars and reduction partials.  LSQR holds
- * v, w and a transposed v (volumes) and u (projections). */
+ * projection vectors with x and b (Section 5) plus the copy, and a small block
+ * of double-precision scalars and reduction partials.  LSQR holds v, w and a
+ * z-fastest copy of v (volumes) and u (projections). */
 kct_status kct_solver_workspace_size(kct_geometry g, kct_dtype dtype, int32_t solver, size_t *bytes);
 
 /* CGLS with delayed residual computation (Section 2, Algorithm 1), with the
- * direction update d = r + beta d.  b: n_rays elements; x: n_vox elements,
- * x0 on entry (unless opts->x0_is_zero), x_K on return.  Breakdown (NR2 = 0 or
+ * direction update d = r + beta d.  b: n_rays elements of `dtype`; x: n_vox
+ * single-precision (float) elements whatever `dtype` is (a 16-bit iterate
+ * stagnates), x0 on entry (unless opts->x0_is_zero), x_K on return.  The
+ * workspace vectors use `dtype`.  Breakdown (NR2 = 0 or
  * NP2 = 0, e.g. b = 0) stops with the current x.  The whole iteration runs on
  * the device without host synchronisation; the call synchronises `stream` once
  * at the end to fill *info (host).  Errors: INVALID_ARG, UNSUPPORTED,

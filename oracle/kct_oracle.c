@@ -276,7 +276,9 @@ void oracle_project_rays(const int32_t *dims, const double *par, const double *a
     }
 }
 
-/* r = A^T y (Eq. 2).  Parallel over z-slabs; every slab visits all rays. */
+/* r = A^T y (Eq. 2).  Parallel over z-slabs; every slab visits all rays.  The
+ * partition does not change the result: a piece's weight does not depend on
+ * the slab it is clipped to, and each voxel sums its pieces in ray order. */
 void oracle_backproject(const int32_t *dims, const double *par, const double *angles,
                         const double *y, double *r)
 {
@@ -284,7 +286,8 @@ void oracle_backproject(const int32_t *dims, const double *par, const double *an
     int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
     memset(r, 0, sizeof(double) * (size_t)nvox);
     int64_t nrays = (int64_t)g.nviews * g.nv * g.nu;
-    int nslab = g.nz < 64 ? g.nz : 64;
+    int nslab = 2 * omp_get_max_threads();
+    if (nslab > g.nz) nslab = g.nz;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int sl = 0; sl < nslab; ++sl) {
         int zlo = (int)((int64_t)g.nz * sl / nslab);

@@ -13,7 +13,8 @@ passes device pointers and the current HIP stream.
 
 Volumes are torch tensors of shape (nz, ny, nx), projections (n_views, nv, nu),
 on the GPU, contiguous, with dtype float32, bfloat16 or float16 (storage type;
-accumulation is single precision and solver scalars double precision).
+accumulation is single precision and solver scalars double precision).  The
+solvers return the iterate x in float32 whatever the storage type of b.
 """
 from __future__ import annotations
 
@@ -211,13 +212,14 @@ class SolveInfo:
 
 
 def _solve(which, g, b, K, x0, err, history, workspace, out):
+    """b (and the workspace vectors) in b's storage dtype; the iterate x is float32."""
     torch = _torch()
     _check_tensor(b, g.proj_shape, "b", g.device)
     if out is None:
-        out = torch.empty(g.vol_shape, dtype=b.dtype, device=g.device)
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=g.device)
     _check_tensor(out, g.vol_shape, "out", g.device)
-    if out.dtype != b.dtype:
-        raise TypeError("out must have b's dtype")
+    if out.dtype != torch.float32:
+        raise TypeError("the solution x is float32 (16-bit iterates stagnate)")
     if x0 is not None:
         _check_tensor(x0, g.vol_shape, "x0", g.device)
         if x0.data_ptr() != out.data_ptr():

@@ -28,15 +28,14 @@ __device__ __forceinline__ double bwd_block_sum(double v)
 }
 
 template <typename T, int EPI>
-__global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
+__global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
                                                   T *__restrict__ out_z, const Scalars *__restrict__ sc,
                                                   double *__restrict__ partials, const int *__restrict__ skip, int nbx,
                                                   int nby, int nbz)
 {
     if (skip && *skip) return;
-    __shared__ float s_e[CH_ROWS * CH_COLS];
+    __shared__ PixStage s_pix[CH_ROWS * CH_COLS];
     __shared__ ColStage s_col[CH_COLS];
-    __shared__ RowStage s_row[CH_ROWS];
     __shared__ int s_fp[4];
 
     // XCD-aware brick assignment
@@ -56,6 +55,11 @@ __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict_
     const float wx0 = g.x0 + (float)(bx * BX) * g.vx, wx1 = g.x0 + (float)ex * g.vx;
     const float wy0 = g.y0 + (float)(by * BY) * g.vy, wy1 = g.y0 + (float)ey * g.vy;
     const float wz0 = g.z0 + (float)iz0 * g.vz, wz1 = g.z0 + (float)(iz0 + nzb) * g.vz;
+
+    // rays parallel to the z-planes lie in z-cell pcell; their staged zc is
+    // that cell's middle (see PixStage)
+    const int pcell = parallel_cell(-g.zc, g.hz);
+    const float pzadd = ((float)pcell - g.hz + 0.5f) + g.zc;
 
     float acc[TZ];
 #pragma unroll
@@ -93,13 +97,19 @@ __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict_
             const int ncol = u1 - cu0 + 1 < CH_COLS ? u1 - cu0 + 1 : CH_COLS;
             for (int cv0 = v0; cv0 <= v1; cv0 += CH_ROWS) {
                 const int nrow = v1 - cv0 + 1 < CH_ROWS ? v1 - cv0 + 1 : CH_ROWS;
-                // 2. stage L * e of the chunk and its ray parameters
+                // 2. stage the chunk: per pixel the z-parameters of its ray and L * e,
+                //    per column the in-plane parameters
                 for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
                     const int r = t / ncol, c = t - r * ncol;
                     const ColParam cp = ck[cu0 + c];
-                    const float qz = g.rows[cv0 + r].qz;
-                    const float L = ray_length_per_xi(cp.lxy2, qz, cp.gp);
-                    s_e[r * CH_COLS + c] = L * to_f32(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
+                    const RowParam rp = g.rows[cv0 + r];
+                    const bool par = rp.inv_qz == 0.0f;
+                    PixStage ps;
+                    ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
+                    ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
+                    ps.le = ray_length_per_xi(cp.lxy2, rp.qz, cp.gp) * to_f32(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
+                    ps.pad = 0.0f;
+                    s_pix[r * CH_COLS + c] = ps;
                 }
                 if (threadIdx.x < ncol) {
                     const ColParam cp = ck[cu0 + threadIdx.x];
@@ -107,20 +117,12 @@ __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict_
                     cs.eta_c = cp.eta_c;
                     cs.inv_a = cp.inv_a;
                     cs.tcv = cp.tcv;
-                    cs.kz = cp.kz;
                     cs.gz = cp.gp * g.inv_vz;
-                    cs.pad[0] = cs.pad[1] = cs.pad[2] = 0.0f;
                     s_col[threadIdx.x] = cs;
-                } else if (threadIdx.x >= 128 && threadIdx.x - 128 < nrow) {
-                    const RowParam rp = g.rows[cv0 + threadIdx.x - 128];
-                    RowStage rs;
-                    rs.qz = rp.qz;
-                    rs.inv_qz = rp.inv_qz;
-                    s_row[threadIdx.x - 128] = rs;
                 }
                 __syncthreads();
                 // 3. gather
-                if (valid) gather_chunk(g, vp, ix, iy, iz0, nzb, s_e, s_col, s_row, cu0, ncol, cv0, nrow, acc);
+                if (valid) gather_chunk(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
                 __syncthreads();
             }
         }
@@ -136,6 +138,7 @@ __global__ __launch_bounds__(256) void k_backward(GeoDev g, const T *__restrict_
             float o;
             if (EPI == BWD_LSQR0) o = (float)sc->bwd_c1 * acc[j];
             else if (EPI == BWD_LSQR) o = (float)sc->bwd_c1 * acc[j] - (float)sc->bwd_c2 * to_f32(out[vox]);
+            else if (EPI == BWD_NORM) o = sc->bwd_scale * acc[j];
             else o = acc[j];
             const T st = from_f32<T>(o);
             out[vox] = st;

@@ -105,7 +105,11 @@ template <> kct_dtype dtype_of<_Float16>() { return KCT_F16; }
         }                                                                                        \
     } while (0)
 
-__global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *history)
+struct StorageScales {
+    double sr, sp, sw;
+};
+
+__global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *history, StorageScales ss)
 {
     if (threadIdx.x != 0) return;
     Scalars s;
@@ -113,7 +117,49 @@ __global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *his
     s.maxiter = maxiter;
     s.err = err;
     s.history = history;
+    s.sr = ss.sr;
+    s.sp = ss.sp;
+    s.sw = ss.sw;
+    s.fwd_scale = (float)(ss.sr / ss.sp);
+    s.bwd_scale = (float)(1.0 / ss.sr);
     *sc = s;
+}
+
+double pow2_at_least(double v) { return std::exp2(std::ceil(std::log2(v))); }
+
+// Storage scales of the solvers' work vectors.  FP32 and BF16 have the range
+// of single precision and use 1 (every scaling is then an exact no-op).  FP16
+// (largest finite 65504, smallest normal 6.1e-5) stores, as powers of two:
+//  - CGLS r and d divided by a bound C on the column sums of A, so that
+//    |r| <= C |e|_inf stays on the scale of e (and b); p divided by C R,
+//    with R a bound on the row sums of A, so |p| <= R |d| does too;
+//  - LSQR w, which is a unit-norm vector of n elements, multiplied by
+//    about sqrt(n) so its elements are of order one.
+// Bounds: a ray crosses the volume over at most its diagonal (R); in one view
+// a voxel meets the rays of at most (footprint columns) x (footprint rows)
+// pixels, each over at most the voxel diagonal (C).
+StorageScales storage_scales(const Geometry *g, kct_dtype t)
+{
+    StorageScales s{1.0, 1.0, 1.0};
+    if (t != KCT_F16) return s;
+    const kct_volume_desc &v = g->vol;
+    const kct_cone_desc &c = g->cone;
+    const double ex = v.nx * v.vx, ey = v.ny * v.vy, ez = v.nz * v.vz;
+    const double R = std::sqrt(ex * ex + ey * ey + ez * ez);
+    double rmax = 0.0;  // largest distance of a volume corner from the rotation axis
+    for (int i = 0; i < 4; ++i) {
+        const double x = v.cx + ((i & 1) ? 0.5 : -0.5) * ex, y = v.cy + ((i & 2) ? 0.5 : -0.5) * ey;
+        rmax = std::fmax(rmax, std::sqrt(x * x + y * y));
+    }
+    const double mag = c.sdd / std::fmax(c.sid - rmax, 1e-6 * c.sid);  // the volume lies inside the orbit
+    const double dvox = std::sqrt(v.vx * v.vx + v.vy * v.vy + v.vz * v.vz);
+    const double dxy = std::sqrt(v.vx * v.vx + v.vy * v.vy);
+    const double cols = std::ceil(mag * dxy / c.du) + 1.0, rows = std::ceil(mag * dvox / c.dv) + 1.0;
+    const double C = (double)c.n_views * cols * rows * dvox;
+    s.sr = pow2_at_least(C);
+    s.sp = s.sr * pow2_at_least(R);
+    s.sw = 1.0 / pow2_at_least(std::sqrt((double)nvox(g)));
+    return s;
 }
 
 template <typename T>
@@ -124,9 +170,9 @@ kct_status project_t(const Geometry *g, const void *x, void *b, void *ws, hipStr
     T *vz = nullptr;
     if (ws) {
         vz = (T *)ws;
-        KCT_TRY(launch_zfast_copy<T>(g->dev, vol, vz, st));
+        KCT_TRY((launch_zfast_copy<T, T>(g->dev, vol, vz, st)));
     }
-    KCT_TRY(launch_forward<T>(g->dev, vol, vz, (T *)b, nullptr, FWD_PLAIN, nullptr, nullptr, nullptr, st));
+    KCT_TRY((launch_forward<T, T>(g->dev, vol, vz, (T *)b, nullptr, FWD_PLAIN, nullptr, nullptr, nullptr, st)));
     return KCT_OK;
 }
 
@@ -171,25 +217,28 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     T *d = (T *)(w + L.v0), *dz = (T *)(w + L.v1), *r = (T *)(w + L.v2);
     T *e = (T *)(w + L.p0), *p = (T *)(w + L.p1);
     const T *b = (const T *)bv;
-    T *x = (T *)xv;
+    float *x = (float *)xv;
     const GeoDev &G = g->dev;
     const int64_t n = nvox(g), m = nrays(g);
     const int64_t nf = forward_num_blocks(G), nbk = backward_num_blocks(G), ns = stream_num_blocks();
     const int K = o->max_iter;
     const int *done = &sc->done;
 
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history,
+                       storage_scales(g, dtype_of<T>()));
     KCT_TRY(hipGetLastError());
     // NB0 = |b|
     KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
     KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
     // x = x0; p = A x; e = b - p
     if (o->x0_is_zero) {
-        KCT_TRY(launch_fill_zero<T>(x, n, st));
+        KCT_TRY(launch_fill_zero<float>(x, n, st));
         KCT_TRY(launch_copy<T>(b, e, m, st));
     } else {
-        KCT_TRY(launch_zfast_copy<T>(G, x, dz, st));
-        KCT_TRY(launch_forward<T>(G, x, dz, e, b, FWD_BMINUS, sc, part, done, st));
+        // single-precision z-fastest copy of x0 in the (not yet used) d and d_z space
+        float *xz0 = (float *)(w + L.v0);
+        KCT_TRY((launch_zfast_copy<float, float>(G, x, xz0, st)));
+        KCT_TRY((launch_forward<float, T>(G, x, xz0, e, b, FWD_BMINUS, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_NB_INIT, st));
     }
     // r = A^T e; d = r; NR2_old = |r|^2
@@ -197,7 +246,7 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     KCT_TRY(launch_finalize(sc, part, nbk, F_NR2_INIT, st));
     KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 1, st));
     // p = A d; NP2 = |p|^2; alpha = NR2_old / NP2
-    KCT_TRY(launch_forward<T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st));
+    KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
     KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
     // x = x + alpha d; e = e - alpha p; NB = |e|; i = 1
     KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
@@ -210,7 +259,7 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         // d = r + beta d
         KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 0, st));
         // p = A d; NP2; alpha
-        KCT_TRY(launch_forward<T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st));
+        KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
         // x += alpha d; e -= alpha p; NB; i = i + 1 (and the while test)
         KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
@@ -234,26 +283,29 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     T *v = (T *)(wp + L.v0), *vz = (T *)(wp + L.v1), *w = (T *)(wp + L.v2);
     T *u = (T *)(wp + L.p0);
     const T *b = (const T *)bv;
-    T *x = (T *)xv;
+    float *x = (float *)xv;
     const GeoDev &G = g->dev;
     const int64_t n = nvox(g), m = nrays(g);
     const int64_t nf = forward_num_blocks(G), nbk = backward_num_blocks(G), ns = stream_num_blocks();
     const int K = o->max_iter;
     const int *done = &sc->done;
 
-    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history,
+                       storage_scales(g, dtype_of<T>()));
     KCT_TRY(hipGetLastError());
     KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
     KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
     // beta u = b - A x0
     if (o->x0_is_zero) {
-        KCT_TRY(launch_fill_zero<T>(x, n, st));
+        KCT_TRY(launch_fill_zero<float>(x, n, st));
         KCT_TRY(launch_copy<T>(b, u, m, st));
         KCT_TRY(launch_norm2<T>(u, m, part, done, st));
         KCT_TRY(launch_finalize(sc, part, ns, F_L_BETA0, st));
     } else {
-        KCT_TRY(launch_zfast_copy<T>(G, x, vz, st));
-        KCT_TRY(launch_forward<T>(G, x, vz, u, b, FWD_BMINUS, sc, part, done, st));
+        // single-precision z-fastest copy of x0 in the (not yet used) v and v_z space
+        float *xz0 = (float *)(wp + L.v0);
+        KCT_TRY((launch_zfast_copy<float, float>(G, x, xz0, st)));
+        KCT_TRY((launch_forward<float, T>(G, x, xz0, u, b, FWD_BMINUS, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA0, st));
     }
     // alpha v = A^T u; w = v
@@ -262,7 +314,7 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 1, n, st));
     for (int it = 0; it < K; ++it) {
         // beta u = A v - alpha u
-        KCT_TRY(launch_forward<T>(G, v, vz, u, nullptr, FWD_LSQR, sc, part, done, st));
+        KCT_TRY((launch_forward<T, T>(G, v, vz, u, nullptr, FWD_LSQR, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA, st));
         // alpha v = A^T u - beta v (skipped on the last iteration), Givens rotation
         KCT_TRY(launch_backward<T>(G, u, v, vz, BWD_LSQR, sc, part, &sc->skip_bwd, st));

@@ -146,6 +146,8 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
     d.dv = (float)cone.dv;
     d.off_u = (float)cone.off_u;
     d.off_v = (float)cone.off_v;
+    d.inv_du = (float)(1.0 / cone.du);
+    d.inv_dv = (float)(1.0 / cone.dv);
     d.cu = 0.5f * (float)(nu - 1);
     d.cv = 0.5f * (float)(nv - 1);
     d.cols = nullptr;

@@ -6,13 +6,13 @@
 // one (x, y) position and the TZ voxels above it.  For every view the
 // workgroup
 //   1. bounds the brick's shadow on the detector (the eight projected corners),
-//   2. stages the shadow's pixels into LDS, already multiplied by the ray
-//      length factor L of their ray, together with the per-column and per-row
-//      ray parameters,
-//   3. lets each lane gather: candidate columns from a bound on its voxel
-//      column's projection, the in-plane xi-interval of each column's rays in
-//      the voxel column (shared by the TZ voxels), candidate rows from the
-//      z-range of those rays, and for every candidate the exact weight of
+//   2. stages, for every pixel of the shadow, the ray's z-parameters and its
+//      value multiplied by the ray length factor L in LDS (one 16-byte record
+//      per pixel), and the per-column in-plane ray parameters,
+//   3. lets each lane gather: the exact interval of detector columns whose
+//      rays cross its voxel column, the in-plane xi-interval of each of those
+//      columns (shared by the TZ voxels), per voxel the candidate rows from
+//      the z-range of those rays, and for every candidate the exact weight of
 //      kct_weights.h.
 // The shadow is staged in chunks of at most CH_COLS x CH_ROWS pixels, so any
 // geometry works; typical bricks need one chunk.
@@ -25,30 +25,38 @@
 
 namespace kct {
 
-constexpr int BX = 16, BY = 16, TZ = 16;  // brick; BX * BY = 256 lanes
+constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
 constexpr int CH_COLS = 48, CH_ROWS = 40;  // staged shadow chunk
+constexpr int NH = 4;                      // detector columns held in registers at once
 
-struct ColStage {   // per staged detector column
-    float eta_c, inv_a, tcv, kz;
-    float gz;       // d T / d xi with T = (segment fraction) / vz
-    float pad[3];
+struct ColStage {  // per staged detector column: in-plane ray parameters
+    float eta_c, inv_a, tcv;
+    float gz;      // d T / d xi with T = (segment fraction) / vz
 };
 
-struct RowStage {   // per staged detector row
-    float qz, inv_qz;
+// Per staged pixel.  zc and czr are zeta at xi = 0 and d xi / d zeta of the
+// pixel's ray (zeta_centre and zeta_inv_slope of its row and column).  A row
+// whose rays are parallel to the z-planes (qz == 0) is staged with czr = +inf
+// and zc moved to the middle of the z-cell those rays lie in: the crossings of
+// every z-plane are then +-inf and the general formula gives exactly the
+// parallel-ray weights of kct_weights.h.
+struct PixStage {
+    float zc, czr;
+    float le;      // L * e
+    float pad;
 };
 
 // Detector coordinates (column, row; fractional pixel indices) of the ray
-// through world point (px, py, pz) in view vp.
+// through world point (px, py, pz) in view vp.  Used for bounds only.
 __host__ __device__ __forceinline__ void project_point(const GeoDev &g, const ViewParam &vp, float px, float py,
                                                        float pz, float &fu, float &fv)
 {
     const float dx = px - vp.sx, dy = py - vp.sy;
     const float num = -vp.s * dx + vp.c * dy;
     const float den = -vp.c * dx - vp.s * dy;  // depth along the central ray (> 0)
-    const float sc = g.sdd / den;
-    fu = (num * sc - g.off_u) / g.du + g.cu;
-    fv = (pz * sc - g.off_v) / g.dv + g.cv;
+    const float sc = g.sdd * __builtin_amdgcn_rcpf(den);
+    fu = (num * sc - g.off_u) * g.inv_du + g.cu;
+    fv = (pz * sc - g.off_v) * g.inv_dv + g.cv;
 }
 
 // Candidate detector columns [ua, ub] of the voxel column whose in-plane centre
@@ -62,72 +70,107 @@ __host__ __device__ __forceinline__ void voxel_columns(const GeoDev &g, const Vi
     const float den = -vp.c * dx - vp.s * dy;
     const float dn = 0.5f * (g.vx * fabsf(vp.s) + g.vy * fabsf(vp.c));  // half extent along e_u
     const float dd = 0.5f * (g.vx * fabsf(vp.c) + g.vy * fabsf(vp.s));  // half extent along depth
-    const float inv = 1.0f / den;
-    const float inv2 = 1.0f / (den - dd);
+    const float inv = __builtin_amdgcn_rcpf(den);
+    const float inv2 = __builtin_amdgcn_rcpf(den - dd);
     const float uc = g.sdd * num * inv;
     const float hw = g.sdd * (dn + dd * fabsf(num) * inv) * inv2;
-    const float fc = (uc - g.off_u) / g.du + g.cu;
-    const float hc = hw / g.du + 1e-3f;
+    const float fc = (uc - g.off_u) * g.inv_du + g.cu;
+    const float hc = hw * g.inv_du + 0.01f;
     ua = (int)ceilf(fc - hc);
     ub = (int)floorf(fc + hc);
 }
 
+// xi-interval [lo, hi] in which the rays of a detector column cross the voxel
+// column whose xi-cell starts at lo_xi and whose eta-cell is ieta (empty when
+// hi <= lo).
+__host__ __device__ __forceinline__ void column_interval(const ColStage &cs, float lo_xi, int ieta, float heta,
+                                                         float &lo, float &hi)
+{
+    float lo_e, hi_e;
+    cell_range(ieta, heta, cs.eta_c, cs.inv_a, lo_e, hi_e);
+    lo = fmaxf(lo_xi, lo_e);
+    hi = fminf(lo_xi + 1.0f, hi_e);
+}
+
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
 // accumulators of its voxels (ix, iy, iz0 + j), j < nzb, for every staged ray
-// i = (column cu0 + c, row cv0 + r).  s_e[r * CH_COLS + c] holds L_i e_i.
+// i = (column cu0 + c, row cv0 + r); s_pix[r * CH_COLS + c] describes ray i.
 __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const ViewParam &vp, int ix, int iy, int iz0,
-                                                      int nzb, const float *s_e, const ColStage *s_col,
-                                                      const RowStage *s_row, int cu0, int ncol, int cv0, int nrow,
-                                                      float (&acc)[TZ])
+                                                      int nzb, const PixStage *s_pix, const ColStage *s_col, int cu0,
+                                                      int ncol, int cv0, int nrow, float (&acc)[TZ])
 {
     int ixi, ieta;
     float hxi, heta;
     if (vp.dom == 0) { ixi = ix; ieta = iy; hxi = g.hx; heta = g.hy; }
     else { ixi = iy; ieta = ix; hxi = g.hy; heta = g.hx; }
     const float lo_xi = (float)ixi - hxi;
-    const float hi_xi = lo_xi + 1.0f;
     int ua, ub;
     voxel_columns(g, vp, g.x0 + ((float)ix + 0.5f) * g.vx, g.y0 + ((float)iy + 0.5f) * g.vy, ua, ub);
     ua = ua < cu0 ? cu0 : ua;
     ub = ub > cu0 + ncol - 1 ? cu0 + ncol - 1 : ub;
+    // The columns whose rays cross the voxel column form an interval (the
+    // rays of consecutive columns fan out monotonically from the source):
+    // narrow the bound to its first and last hit.
+    int ha = ub + 1, hb = ub;  // empty unless a column is hit
+    for (int iu = ua; iu <= ub; ++iu) {
+        float lo, hi;
+        column_interval(s_col[iu - cu0], lo_xi, ieta, heta, lo, hi);
+        if (hi > lo) {
+            ha = iu < ha ? iu : ha;
+            hb = iu;
+        }
+    }
     const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (centred index)
     const float zz0 = mbz0 + g.zc;         // the same plane as a height above the source plane
-    const float vofs = -g.off_v / g.dv + g.cv;
+    const float vofs = -g.off_v * g.inv_dv + g.cv;
     const int vmax = cv0 + nrow - 1;
-    for (int iu = ua; iu <= ub; ++iu) {
-        const ColStage cs = s_col[iu - cu0];
-        float lo_e, hi_e;
-        cell_range(ieta, heta, cs.eta_c, cs.inv_a, lo_e, hi_e);
-        const float lo = fmaxf(lo_xi, lo_e), hi = fminf(hi_xi, hi_e);
-        if (!(hi > lo)) continue;
-        // Rows: a ray of height qz is at zeta = qz * T - zc, T = tcv + xi * gz > 0;
-        // inside [lo, hi] it meets the z-cell [zz, zz + 1] (heights) only if
-        // qz lies in [zz, zz + 1] / [Tmin, Tmax].
-        const float T1 = cs.tcv + lo * cs.gz, T2 = cs.tcv + hi * cs.gz;
-        const float ra = 1.0f / (fmaxf(T1, T2) * g.dv), rb = 1.0f / (fminf(T1, T2) * g.dv);
+    for (int c0 = ha; c0 <= hb; c0 += NH) {
+        // xi-intervals of up to NH hit columns, and the range of T = tcv + xi gz
+        // over them (a ray of height qz is at height qz T above the source plane)
+        const int nh = hb - c0 + 1 < NH ? hb - c0 + 1 : NH;
+        float lo[NH], hi[NH];
+        float tmin = INFINITY, tmax = 0.0f;
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+            const int c = h < nh ? c0 + h : c0;
+            const ColStage cs = s_col[c - cu0];
+            column_interval(cs, lo_xi, ieta, heta, lo[h], hi[h]);
+            if (h < nh && hi[h] > lo[h]) {
+                const float T1 = cs.tcv + lo[h] * cs.gz, T2 = cs.tcv + hi[h] * cs.gz;
+                tmin = fminf(tmin, fminf(T1, T2));
+                tmax = fmaxf(tmax, fmaxf(T1, T2));
+            }
+        }
+        if (!(tmax > 0.0f)) continue;  // no column of this group is hit
+        // Rows: inside these columns a ray of row height qz meets the z-cell with
+        // planes at heights [zz, zz + 1] only if qz lies in [zz, zz + 1] / [Tmin, Tmax].
+        const float ra = __builtin_amdgcn_rcpf(tmax) * g.inv_dv, rb = __builtin_amdgcn_rcpf(tmin) * g.inv_dv;
         float pa = zz0 * ra, pb = zz0 * rb;
-        const float *e_col = s_e + (iu - cu0);
 #pragma unroll
         for (int j = 0; j < TZ; ++j) {
-            if (j < nzb) {
             const float zz1 = zz0 + (float)(j + 1);
             const float na = zz1 * ra, nb = zz1 * rb;
             const float vlo = fminf(pa, pb) + vofs, vhi = fmaxf(na, nb) + vofs;
             pa = na;
             pb = nb;
-            int va = (int)ceilf(vlo - 0.01f), vb = (int)floorf(vhi + 0.01f);
-            va = va < cv0 ? cv0 : va;
-            vb = vb > vmax ? vmax : vb;
-            const float mb = mbz0 + (float)j;
-            for (int v = va; v <= vb; ++v) {
-                const RowStage rs = s_row[v - cv0];
-                const float zeta_c = zeta_centre(rs.qz, cs.tcv, g.zc);
-                const float czr = zeta_inv_slope(rs.inv_qz, cs.kz);
-                float lo_z, hi_z;
-                cell_range_mb(iz0 + j, mb, g.hz, zeta_c, czr, lo_z, hi_z);
-                const float w = fminf(hi, hi_z) - fmaxf(lo, lo_z);
-                if (w > 0.0f) acc[j] = __builtin_fmaf(w, e_col[(v - cv0) * CH_COLS], acc[j]);
-            }
+            if (j < nzb) {
+                int va = (int)ceilf(vlo - 0.01f), vb = (int)floorf(vhi + 0.01f);
+                va = va < cv0 ? cv0 : va;
+                vb = vb > vmax ? vmax : vb;
+                const float mb = mbz0 + (float)j;
+                const float mb1 = mb + 1.0f;
+                for (int v = va; v <= vb; ++v) {
+                    const PixStage *prow = s_pix + (v - cv0) * CH_COLS + (c0 - cu0);
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) {
+                        if (h < nh) {
+                            const PixStage p = prow[h];
+                            const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
+                            const float w = fminf(hi[h], fmaxf(b0, b1)) - fmaxf(lo[h], fminf(b0, b1));
+                            if (w > 0.0f) acc[j] = __builtin_fmaf(w, p.le, acc[j]);
+                        }
+                    }
+                }
             }
         }
     }

@@ -61,6 +61,7 @@ struct GeoDev {
     float zc;                // cz / vz
     float inv_vz;
     float sdd, du, dv, off_u, off_v;
+    float inv_du, inv_dv;
     float cu, cv;            // (nu - 1)/2, (nv - 1)/2
     const ColParam *cols;    // [nviews][nu]
     const RowParam *rows;    // [nv]
@@ -76,6 +77,12 @@ struct Scalars {
     double fwd_c1, fwd_c2;   // u_hat' = c1 * (A v_hat) - c2 * u_hat
     double bwd_c1, bwd_c2;   // v_hat' = c1 * (A^T u_hat) - c2 * v_hat
     double x_coef, w_coef, w_vcoef;  // x += x_coef w;  w = w_vcoef v_hat - w_coef w
+    // Storage scales (powers of two; 1 unless the storage type is FP16): a
+    // stored element s represents sigma * s.  CGLS: r and d use sr, p uses sp
+    // (e and b are stored as they are); LSQR: w uses sw.
+    double sr, sp, sw;
+    double x_alpha, e_alpha;         // CGLS: x += x_alpha d;  e -= e_alpha p
+    float fwd_scale, bwd_scale;      // CGLS epilogues: p = fwd_scale * (A d), r = bwd_scale * (A^T e)
     double err;
     double *history;
     int iters, done, stop, maxiter;
@@ -127,8 +134,9 @@ struct bf16 {
 };
 
 // Kernel launchers (defined in the .hip files).
-template <typename T>
-hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_z, T *out, const T *aux, int epi,
+// Forward projection with volume storage TV and projection storage TP.
+template <typename TV, typename TP>
+hipError_t launch_forward(const GeoDev &g, const TV *vol, const TV *vol_z, TP *out, const TP *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st);
 // vol_z (optional): the same volume stored z-fastest, vol_z[(iy * nx + ix) * nz + iz].
 // out_z (LSQR epilogues only): receives the output in that layout as well.
@@ -141,18 +149,20 @@ int64_t backward_num_blocks(const GeoDev &g);
 // Vector kernels (vector_ops.hip).
 int64_t stream_num_blocks();
 // dst[(iy * nx + ix) * nz + iz] = src[(iz * ny + iy) * nx + ix]
-template <typename T>
-hipError_t launch_zfast_copy(const GeoDev &g, const T *src, T *dst, hipStream_t st);
+template <typename TS, typename TD>
+hipError_t launch_zfast_copy(const GeoDev &g, const TS *src, TD *dst, hipStream_t st);
 template <typename T>
 hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip, hipStream_t st);
 hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st);
 template <typename T>
 hipError_t launch_fill_zero(T *v, int64_t n, hipStream_t st);
+// The solvers keep the iterate x in single precision whatever the storage type
+// of the other vectors (16-bit iterates stagnate).
 template <typename T>
 hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st);
 // x += alpha d
 template <typename T>
-hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st);
+hipError_t launch_cgls_x(float *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st);
 // d = r (+ beta d) and its z-fastest copy
 template <typename T>
 hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first,
@@ -162,6 +172,6 @@ template <typename T>
 hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double *partials, hipStream_t st);
 // LSQR: w = w_vcoef v (init) or x += x_coef w; w = w_vcoef v - w_coef w
 template <typename T>
-hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st);
+hipError_t launch_lsqr_xw(float *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st);
 
 }  // namespace kct

@@ -12,30 +12,94 @@
 
 namespace kct {
 
-// Walk one ray through the volume and return sum_j (xi-length in voxel j) * x_j.
+// z-walk state of one ray: current z-cell mz (-1 / nz stand for "below" /
+// "above" the volume), walking direction stz, index hb of the plane where the
+// walk leaves mz, and the crossings lz (entry into mz) and hzv (exit from mz).
+struct ZWalk {
+    int mz, stz, hb;
+    float lz, hzv, zeta_c, czr;
+};
+
+// Start the z-walk of a ray at the in-plane entry t_start: at the cell of
+// t_start or one before it along the ray (clamped to the sentinels); the first
+// piece then moves on.  A ray that never meets the volume in [t_start, t_end]
+// gets an inert state (no piece has positive weight, nothing is read).
+__host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, float czr, int nz, float hz,
+                                                    float t_start, float t_end)
+{
+    s.zeta_c = zeta_c;
+    s.czr = czr;
+    if (czr == 0.0f) {
+        s.mz = parallel_cell(zeta_c, hz);
+        s.stz = 0;
+        s.hb = 0;
+        s.lz = -INFINITY;
+        s.hzv = INFINITY;
+        if (s.mz < 0 || s.mz >= nz) { s.mz = -1; s.lz = INFINITY; }
+        return;
+    }
+    const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at(hz, zeta_c, czr);
+    if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) {
+        s.mz = -1;
+        s.stz = 0;
+        s.hb = 0;
+        s.lz = INFINITY;
+        s.hzv = INFINITY;
+        return;
+    }
+    s.stz = czr > 0.0f ? 1 : -1;
+    const int m = (int)floorf(zeta_c + t_start / czr + hz) - s.stz;
+    s.mz = m < -1 ? -1 : (m > nz ? nz : m);
+    s.hb = s.stz > 0 ? s.mz + 1 : s.mz;
+    const int lb = s.hb - s.stz;
+    s.lz = (lb >= 0 && lb <= nz) ? cross_at((float)lb - hz, zeta_c, czr) : -INFINITY;
+    s.hzv = (s.hb >= 0 && s.hb <= nz) ? cross_at((float)s.hb - hz, zeta_c, czr) : INFINITY;
+}
+
+// Add the ray's part inside the in-plane piece [t0, t1] (in-plane cell at
+// volume offset base) to acc, stepping through z-cells while the ray crosses
+// z-planes before t1.
+template <typename T>
+__host__ __device__ __forceinline__ void zwalk_piece(ZWalk &s, const T *__restrict__ vol, int base, int sz, int nz,
+                                                     float hz, float t0, float t1, float &acc)
+{
+    for (int guard = nz + 2; guard > 0; --guard) {
+        const float w = fminf(t1, s.hzv) - fmaxf(t0, s.lz);
+        if (w > 0.0f && (unsigned)s.mz < (unsigned)nz) acc = __builtin_fmaf(w, to_f32(vol[base + s.mz * sz]), acc);
+        if (!(s.hzv < t1)) break;
+        s.lz = s.hzv;
+        s.mz += s.stz;
+        s.hb += s.stz;
+        s.hzv = (s.hb >= 0 && s.hb <= nz) ? cross_at((float)s.hb - hz, s.zeta_c, s.czr) : INFINITY;
+    }
+}
+
+// Walk R rays of one detector column (rows differ, so zeta_c and czr differ)
+// through the volume and return sum_j (xi-length in voxel j) * x_j per ray.
 //
-// The walk is split so that a wavefront whose lanes are rays of one detector
-// column (different rows) does identical in-plane work in every lane:
+// The walk is split so that rays of one detector column do identical in-plane
+// work and share it:
 //   * the in-plane walk (xi and eta planes) depends on the column only; it
-//     enumerates the pieces [t0, t1] of the ray's shadow in the (x, y) plane,
+//     enumerates the pieces [t0, t1] of the rays' shadow in the (x, y) plane,
 //     one per in-plane cell, in increasing xi;
-//   * the zeta walk is per lane: inside each in-plane piece the lane adds the
-//     piece's part in its current z-cell and steps to the next z-cell when the
-//     ray crosses a z-plane before t1 (rare: z-slopes are small).
+//   * the zeta walk is per ray: inside each in-plane piece the ray adds the
+//     piece's part in its current z-cell and steps to the next z-cell when it
+//     crosses a z-plane before t1 (rare: z-slopes are small).
 // Every weight is min(the three highs) - max(the three lows) of kct_weights.h:
 // t0 equals the larger in-plane low (the walk starts at an exact cell and t0 is
 // always the crossing at which the current in-plane cell was entered).
 // Volume addressing: element (zeta cell m, xi cell i, eta cell e) is at
 // vol[m * sz + i * sxi + e * seta].  With the z-fastest copy of the volume
-// (sz = 1) the 64 lanes of a wavefront read neighbouring addresses.
-// z-cells -1 and nz stand for "below" and "above" the volume: nothing is read
-// there, and the crossing out of the volume is never followed back.
-template <typename T>
-__host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ vol, int sxi, int seta, int sz, int nxi,
+// (sz = 1), lanes that hold neighbouring rows read neighbouring addresses.
+template <typename T, int R>
+__host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, int sxi, int seta, int sz, int nxi,
                                                     int neta, int nz, float hxi, float heta, float hz, float eta_c,
-                                                    float inv_a, float a, float zeta_c, float czr)
+                                                    float inv_a, float a, const float (&zeta_c)[R],
+                                                    const float (&czr)[R], float (&acc)[R])
 {
-    // In-plane extent [t_start, t_end] of the ray inside the volume's (x, y) box.
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    // In-plane extent [t_start, t_end] of the rays inside the volume's (x, y) box.
     float lo_e, hi_e;
     if (inv_a == 0.0f) {
         const int m = parallel_cell(eta_c, heta);
@@ -49,15 +113,15 @@ __host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ vol, i
     }
     const float t_start = fmaxf(-hxi, lo_e);
     const float t_end = fminf(hxi, hi_e);
-    if (!(t_end > t_start)) return 0.0f;
-    // This lane's extent in z; a ray that never meets the volume does nothing.
-    if (czr == 0.0f) {
-        const int m = parallel_cell(zeta_c, hz);
-        if (m < 0 || m >= nz) return 0.0f;
-    } else {
-        const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at(hz, zeta_c, czr);
-        if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) return 0.0f;
+    if (!(t_end > t_start)) return;
+    ZWalk zs[R];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        zwalk_init(zs[r], zeta_c[r], czr[r], nz, hz, t_start, t_end);
+        any = any || zs[r].hzv != INFINITY || zs[r].lz != INFINITY;
     }
+    if (!any) return;
 
     // Exact in-plane cells at t_start: lo <= t_start < hi on both axes.
     int mx = (int)floorf(t_start + hxi);
@@ -93,42 +157,14 @@ __host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ vol, i
         }
     }
 
-    // z state: start at the cell of t_start or one before it along the ray
-    // (clamped to the sentinels -1 / nz); the first piece then moves on.
-    int mz, stz, hb;
-    float lz, hzv;
-    if (czr == 0.0f) {
-        mz = parallel_cell(zeta_c, hz);
-        stz = 0;
-        hb = 0;
-        lz = -INFINITY;
-        hzv = INFINITY;
-    } else {
-        stz = czr > 0.0f ? 1 : -1;
-        int m = (int)floorf(zeta_c + t_start / czr + hz) - stz;
-        mz = m < -1 ? -1 : (m > nz ? nz : m);
-        hb = stz > 0 ? mz + 1 : mz;
-        const int lb = hb - stz;
-        lz = (lb >= 0 && lb <= nz) ? cross_at((float)lb - hz, zeta_c, czr) : -INFINITY;
-        hzv = (hb >= 0 && hb <= nz) ? cross_at((float)hb - hz, zeta_c, czr) : INFINITY;
-    }
-
     int base = mx * sxi + me * seta;
     const int de = ste * seta;
     const float fste = (float)ste;
-    float acc = 0.0f;
     float t0 = t_start;
     for (int guard = nxi + neta + 4; t0 < t_end && guard > 0; --guard) {
         const float t1 = fminf(hx, he);
-        for (int zg = nz + 2; zg > 0; --zg) {
-            const float w = fminf(t1, hzv) - fmaxf(t0, lz);
-            if (w > 0.0f && (unsigned)mz < (unsigned)nz) acc = __builtin_fmaf(w, to_f32(vol[base + mz * sz]), acc);
-            if (!(hzv < t1)) break;
-            lz = hzv;
-            mz += stz;
-            hb += stz;
-            hzv = (hb >= 0 && hb <= nz) ? cross_at((float)hb - hz, zeta_c, czr) : INFINITY;
-        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) zwalk_piece<T>(zs[r], vol, base, sz, nz, hz, t0, t1, acc[r]);
         if (hx == t1) {
             hx += 1.0f;
             base += sxi;
@@ -140,7 +176,6 @@ __host__ __device__ __forceinline__ float trace_ray(const T *__restrict__ vol, i
         }
         t0 = t1;
     }
-    return acc;
 }
 
 }  // namespace kct

@@ -1,8 +1,8 @@
 // projector.hip -- the forward cone-beam projector for gfx950.
 //
 //   forward  p = A x    (Section 2, Eq. 1): ray-driven.  One lane per ray; the
-//            64 lanes of a wavefront are 64 neighbouring detector rows of one
-//            column.  Their rays share the in-plane part of the walk (identical
+//            lanes of a wavefront hold neighbouring detector rows of one
+//            column (FWD_R rows per lane).  Their rays share the in-plane part of the walk (identical
 //            work in every lane, no divergence), differ only in z, and read a
 //            copy of the volume stored z-fastest, so one gather instruction of
 //            the wavefront touches a few neighbouring cache lines.  Each lane
@@ -19,7 +19,8 @@
 namespace kct {
 
 constexpr int FWD_COLS = 4;    // detector columns per workgroup (one per wavefront)
-constexpr int FWD_ROWS = 64;   // detector rows per wavefront (one per lane)
+constexpr int FWD_R = 2;       // detector rows per lane
+constexpr int FWD_ROWS = 64 * FWD_R;  // detector rows per wavefront
 constexpr int NXCD = 8;
 
 // Sum of v over the 256 threads of the workgroup, in a fixed order.  Result is
@@ -56,9 +57,9 @@ __host__ __device__ __forceinline__ FwdGrid fwd_grid(const GeoDev &g)
 // volume) over many views.  Dispatch fills the eight XCDs round-robin; within
 // every 64 consecutive workgroups the order is permuted so that each XCD gets 8
 // neighbouring column groups, which share voxels in that XCD's L2.
-template <typename T, int EPI>
-__global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__ vol, const T *__restrict__ vol_z,
-                                                 T *__restrict__ out, const T *__restrict__ aux,
+template <typename TV, typename TP, int EPI>
+__global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+                                                 TP *__restrict__ out, const TP *__restrict__ aux,
                                                  const Scalars *__restrict__ sc, double *__restrict__ partials,
                                                  const int *__restrict__ skip)
 {
@@ -72,13 +73,12 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
     const int k = (int)(rest % fg.nviews);
     const int band = (int)(rest / fg.nviews);
     const int iu = cg * FWD_COLS + (int)(threadIdx.x >> 6);
-    const int iv = band * FWD_ROWS + (int)(threadIdx.x & 63);
+    const int lane = (int)(threadIdx.x & 63);
     const ViewParam vp = g.views[k];
-    const bool valid = iu < g.nu && iv < g.nv;
 
     int nxi, neta, sxi, seta, sz;
     float hxi, heta;
-    const T *base;
+    const TV *base;
     if (vp.dom == 0) {  // xi = x, eta = y
         nxi = g.nx; neta = g.ny; hxi = g.hx; heta = g.hy;
         if (vol_z) { base = vol_z; sz = 1; sxi = g.nz; seta = g.nx * g.nz; }
@@ -89,28 +89,47 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
         else { base = vol; sz = g.nx * g.ny; sxi = g.nx; seta = 1; }
     }
 
-    float p = 0.0f;
-    if (valid) {
-        const ColParam cp = g.cols[(size_t)k * g.nu + iu];
-        const RowParam rp = g.rows[iv];
-        const float zeta_c = zeta_centre(rp.qz, cp.tcv, g.zc);
-        const float czr = zeta_inv_slope(rp.inv_qz, cp.kz);
-        const float L = ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
-        const float s = trace_ray<T>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a,
-                                     zeta_c, czr);
-        p = L * s;
+    // lane rows: band * FWD_ROWS + lane + 64 r
+    float zc[FWD_R], czr[FWD_R], Ls[FWD_R], p[FWD_R];
+    bool ok[FWD_R];
+    const bool col_ok = iu < g.nu;
+    ColParam cp{};
+    if (col_ok) cp = g.cols[(size_t)k * g.nu + iu];
+#pragma unroll
+    for (int r = 0; r < FWD_R; ++r) {
+        const int iv = band * FWD_ROWS + lane + 64 * r;
+        ok[r] = col_ok && iv < g.nv;
+        const RowParam rp = ok[r] ? g.rows[iv] : RowParam{0.0f, 0.0f};
+        zc[r] = zeta_centre(rp.qz, cp.tcv, g.zc);
+        czr[r] = zeta_inv_slope(rp.inv_qz, cp.kz);
+        Ls[r] = ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
+        if (!ok[r]) czr[r] = 1.0f, zc[r] = 3.0e30f;  // far outside: an inert ray
     }
-    const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
+    if (col_ok) {
+        float s[FWD_R];
+        trace_rays<TV, FWD_R>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc, czr,
+                             s);
+#pragma unroll
+        for (int r = 0; r < FWD_R; ++r) p[r] = Ls[r] * s[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < FWD_R; ++r) p[r] = 0.0f;
+    }
     double sq = 0.0;
-    if (valid) {
+#pragma unroll
+    for (int r = 0; r < FWD_R; ++r) {
+        if (!ok[r]) continue;
+        const int iv = band * FWD_ROWS + lane + 64 * r;
+        const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
         float o;
-        if (EPI == FWD_BMINUS) o = to_f32(aux[ray]) - p;
-        else if (EPI == FWD_LSQR) o = (float)sc->fwd_c1 * p - (float)sc->fwd_c2 * to_f32(out[ray]);
-        else o = p;
-        const T st = from_f32<T>(o);
+        if (EPI == FWD_BMINUS) o = to_f32(aux[ray]) - p[r];
+        else if (EPI == FWD_LSQR) o = (float)sc->fwd_c1 * p[r] - (float)sc->fwd_c2 * to_f32(out[ray]);
+        else if (EPI == FWD_NORM) o = sc->fwd_scale * p[r];
+        else o = p[r];
+        const TP st = from_f32<TP>(o);
         out[ray] = st;
         const double od = (double)to_f32(st);
-        sq = od * od;
+        sq += od * od;
     }
     if (EPI != FWD_PLAIN) {
         const double bs = block_sum_256(sq);
@@ -120,25 +139,25 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const T *__restrict__
 
 int64_t forward_num_blocks(const GeoDev &g) { return fwd_grid(g).nblocks; }
 
-template <typename T>
-hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_z, T *out, const T *aux, int epi,
+template <typename TV, typename TP>
+hipError_t launch_forward(const GeoDev &g, const TV *vol, const TV *vol_z, TP *out, const TP *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st)
 {
     dim3 grid((unsigned)fwd_grid(g).nblocks);
     dim3 block(256);
     switch (epi) {
     case FWD_PLAIN:
-        hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<TV, TP, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     case FWD_NORM:
-        hipLaunchKernelGGL((k_forward<T, FWD_NORM>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<TV, TP, FWD_NORM>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     case FWD_BMINUS:
-        hipLaunchKernelGGL((k_forward<T, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
+        hipLaunchKernelGGL((k_forward<TV, TP, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
                            skip);
         break;
     case FWD_LSQR:
-        hipLaunchKernelGGL((k_forward<T, FWD_LSQR>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+        hipLaunchKernelGGL((k_forward<TV, TP, FWD_LSQR>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
         break;
     default:
         return hipErrorInvalidValue;
@@ -146,11 +165,13 @@ hipError_t launch_forward(const GeoDev &g, const T *vol, const T *vol_z, T *out,
     return hipGetLastError();
 }
 
-#define KCT_INST(T)                                                                                              \
-    template hipError_t launch_forward<T>(const GeoDev &, const T *, const T *, T *, const T *, int,            \
-                                          const Scalars *, double *, const int *, hipStream_t);
-KCT_INST(float)
-KCT_INST(bf16)
-KCT_INST(_Float16)
+#define KCT_INST(TV, TP)                                                                                       \
+    template hipError_t launch_forward<TV, TP>(const GeoDev &, const TV *, const TV *, TP *, const TP *, int,   \
+                                               const Scalars *, double *, const int *, hipStream_t);
+KCT_INST(float, float)
+KCT_INST(bf16, bf16)
+KCT_INST(_Float16, _Float16)
+KCT_INST(float, bf16)
+KCT_INST(float, _Float16)
 
 }  // namespace kct

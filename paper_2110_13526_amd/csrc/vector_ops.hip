@@ -59,13 +59,13 @@ __global__ __launch_bounds__(TB) void k_copy(const T *__restrict__ s, T *__restr
 
 // x += alpha d
 template <typename T>
-__global__ __launch_bounds__(TB) void k_cgls_x(T *__restrict__ x, const T *__restrict__ d,
+__global__ __launch_bounds__(TB) void k_cgls_x(float *__restrict__ x, const T *__restrict__ d,
                                                const Scalars *__restrict__ sc, int64_t n)
 {
     if (sc->done) return;
-    const float alpha = (float)sc->alpha;
+    const float alpha = (float)sc->x_alpha;
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB)
-        x[i] = from_f32<T>(to_f32(x[i]) + alpha * to_f32(d[i]));
+        x[i] = x[i] + alpha * to_f32(d[i]);
 }
 
 // e -= alpha p, partial |e|^2
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(TB) void k_cgls_e(T *__restrict__ e, const T *__res
                                                double *__restrict__ partials)
 {
     if (sc->done) return;
-    const float alpha = (float)sc->alpha;
+    const float alpha = (float)sc->e_alpha;
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
         const T v = from_f32<T>(to_f32(e[i]) - alpha * to_f32(p[i]));
@@ -117,26 +117,27 @@ __global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(TB) void k_zfast_copy(int nx, int ny, int nz, const T *__restrict__ s, T *__restrict__ dz)
+template <typename TS, typename TD>
+__global__ __launch_bounds__(TB) void k_zfast_copy(int nx, int ny, int nz, const TS *__restrict__ s,
+                                                   TD *__restrict__ dz)
 {
-    __shared__ T tile[32][33];
+    __shared__ float tile[32][33];
     const int bx = blockIdx.x * 32, bz = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int j = ty; j < 32; j += 8) {
         const int x = bx + tx, z = bz + j;
-        if (x < nx && z < nz) tile[j][tx] = s[((size_t)z * ny + y) * nx + x];
+        if (x < nx && z < nz) tile[j][tx] = to_f32(s[((size_t)z * ny + y) * nx + x]);
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
         const int z = bz + tx, x = bx + j;
-        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = tile[tx][j];
+        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = from_f32<TD>(tile[tx][j]);
     }
 }
 
 // LSQR: init: w = w_vcoef v.  Iteration: x += x_coef w; w = w_vcoef v - w_coef w.
 template <typename T, int INIT>
-__global__ __launch_bounds__(TB) void k_lsqr_xw(T *__restrict__ x, T *__restrict__ w, const T *__restrict__ v,
+__global__ __launch_bounds__(TB) void k_lsqr_xw(float *__restrict__ x, T *__restrict__ w, const T *__restrict__ v,
                                                 const Scalars *__restrict__ sc, int64_t n)
 {
     if (sc->done) return;
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(TB) void k_lsqr_xw(T *__restrict__ x, T *__restrict
     const bool upd_w = sc->w_vcoef != 0.0 || sc->w_coef != 0.0;
     for (int64_t i = (int64_t)blockIdx.x * TB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TB) {
         const float wi = to_f32(w[i]);
-        x[i] = from_f32<T>(to_f32(x[i]) + xc * wi);
+        x[i] = x[i] + xc * wi;
         if (upd_w) w[i] = from_f32<T>(vc * to_f32(v[i]) - wc * wi);
     }
 }
@@ -187,18 +188,26 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         sc->nb = sqrt(S);
         if (!isfinite(sc->nb)) stop(KCT_STOP_NUMERIC);
         break;
-    case F_NR2_INIT:  // NR2_old = |r|^2
-        sc->nr2_old = S;
-        sc->nr2_now = S;
-        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
-        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
+    case F_NR2_INIT: {  // NR2_old = |r|^2 (r is stored divided by sr)
+        const double nr2 = S * (sc->sr * sc->sr);
+        sc->nr2_old = nr2;
+        sc->nr2_now = nr2;
+        if (!isfinite(nr2)) stop(KCT_STOP_NUMERIC);
+        else if (nr2 == 0.0) stop(KCT_STOP_BREAKDOWN);
         break;
-    case F_ALPHA:  // NP2 = |p|^2, alpha = NR2_old / NP2
-        sc->np2 = S;
-        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
-        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
-        else sc->alpha = sc->nr2_old / S;
+    }
+    case F_ALPHA: {  // NP2 = |p|^2, alpha = NR2_old / NP2 (p is stored divided by sp)
+        const double np2 = S * (sc->sp * sc->sp);
+        sc->np2 = np2;
+        if (!isfinite(np2)) stop(KCT_STOP_NUMERIC);
+        else if (np2 == 0.0) stop(KCT_STOP_BREAKDOWN);
+        else {
+            sc->alpha = sc->nr2_old / np2;
+            sc->x_alpha = sc->alpha * sc->sr;
+            sc->e_alpha = sc->alpha * sc->sp;
+        }
         break;
+    }
     case F_NB: {  // NB = |e|, i = i + 1, stop test of the while loop
         const double nb = sqrt(S);
         sc->nb = nb;
@@ -209,15 +218,17 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         else if (sc->iters >= sc->maxiter) stop(KCT_STOP_MAXITER);
         break;
     }
-    case F_BETA:  // NR2_now = |r|^2, beta = NR2_now / NR2_old, NR2_old = NR2_now
-        sc->nr2_now = S;
-        if (!isfinite(S)) stop(KCT_STOP_NUMERIC);
-        else if (S == 0.0) stop(KCT_STOP_BREAKDOWN);
+    case F_BETA: {  // NR2_now = |r|^2, beta = NR2_now / NR2_old, NR2_old = NR2_now
+        const double nr2 = S * (sc->sr * sc->sr);
+        sc->nr2_now = nr2;
+        if (!isfinite(nr2)) stop(KCT_STOP_NUMERIC);
+        else if (nr2 == 0.0) stop(KCT_STOP_BREAKDOWN);
         else {
-            sc->beta = S / sc->nr2_old;
-            sc->nr2_old = S;
+            sc->beta = nr2 / sc->nr2_old;
+            sc->nr2_old = nr2;
         }
         break;
+    }
     case F_L_BETA0: {  // beta_1 = |u_hat|, u = u_hat / beta_1
         const double b = sqrt(S);
         sc->l_beta = b;
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         if (!isfinite(a)) stop(KCT_STOP_NUMERIC);
         else if (a == 0.0) stop(KCT_STOP_BREAKDOWN);
         else {
-            sc->w_vcoef = 1.0 / a;
+            sc->w_vcoef = 1.0 / (a * sc->sw);  // w is stored divided by sw
             sc->fwd_c1 = 1.0 / a;
             sc->fwd_c2 = a / sc->l_beta;
         }
@@ -268,9 +279,9 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         sc->rhobar = -c * a;
         sc->phi = c * sc->phibar;
         sc->phibar = s * sc->phibar;
-        sc->x_coef = sc->phi / rho;
+        sc->x_coef = (sc->phi / rho) * sc->sw;
         sc->w_coef = theta / rho;
-        sc->w_vcoef = a != 0.0 ? 1.0 / a : 0.0;
+        sc->w_vcoef = a != 0.0 ? 1.0 / (a * sc->sw) : 0.0;
         if (a == 0.0) sc->w_coef = 0.0;
         sc->l_alpha = a;
         if (a != 0.0) { sc->fwd_c1 = 1.0 / a; sc->fwd_c2 = a / beta; }
@@ -300,11 +311,11 @@ static dim3 sgrid(int64_t n)
     return dim3((unsigned)b);
 }
 
-template <typename T>
-hipError_t launch_zfast_copy(const GeoDev &g, const T *src, T *dst, hipStream_t st)
+template <typename TS, typename TD>
+hipError_t launch_zfast_copy(const GeoDev &g, const TS *src, TD *dst, hipStream_t st)
 {
     dim3 grid((g.nx + 31) / 32, (g.nz + 31) / 32, g.ny);
-    hipLaunchKernelGGL(k_zfast_copy<T>, grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, src, dst);
+    hipLaunchKernelGGL((k_zfast_copy<TS, TD>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, src, dst);
     return hipGetLastError();
 }
 
@@ -337,7 +348,7 @@ hipError_t launch_copy(const T *src, T *dst, int64_t n, hipStream_t st)
 }
 
 template <typename T>
-hipError_t launch_cgls_x(T *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st)
+hipError_t launch_cgls_x(float *x, const T *d, const Scalars *sc, int64_t n, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cgls_x<T>, sgrid(n), dim3(TB), 0, st, x, d, sc, n);
     return hipGetLastError();
@@ -360,7 +371,7 @@ hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double 
 }
 
 template <typename T>
-hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st)
+hipError_t launch_lsqr_xw(float *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st)
 {
     if (init) hipLaunchKernelGGL((k_lsqr_xw<T, 1>), sgrid(n), dim3(TB), 0, st, x, w, v, sc, n);
     else hipLaunchKernelGGL((k_lsqr_xw<T, 0>), sgrid(n), dim3(TB), 0, st, x, w, v, sc, n);
@@ -368,17 +379,21 @@ hipError_t launch_lsqr_xw(T *x, T *w, const T *v, const Scalars *sc, int init, i
 }
 
 #define KCT_VINST(T)                                                                                       \
-    template hipError_t launch_zfast_copy<T>(const GeoDev &, const T *, T *, hipStream_t);                \
     template hipError_t launch_norm2<T>(const T *, int64_t, double *, const int *, hipStream_t);          \
     template hipError_t launch_fill_zero<T>(T *, int64_t, hipStream_t);                                   \
     template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                             \
-    template hipError_t launch_cgls_x<T>(T *, const T *, const Scalars *, int64_t, hipStream_t);          \
+    template hipError_t launch_cgls_x<T>(float *, const T *, const Scalars *, int64_t, hipStream_t);      \
     template hipError_t launch_cgls_d<T>(const GeoDev &, const T *, T *, T *, const Scalars *, int,       \
                                          hipStream_t);                                                    \
     template hipError_t launch_cgls_e<T>(T *, const T *, const Scalars *, int64_t, double *, hipStream_t); \
-    template hipError_t launch_lsqr_xw<T>(T *, T *, const T *, const Scalars *, int, int64_t, hipStream_t);
+    template hipError_t launch_lsqr_xw<T>(float *, T *, const T *, const Scalars *, int, int64_t, hipStream_t);
 KCT_VINST(float)
 KCT_VINST(bf16)
 KCT_VINST(_Float16)
+
+#define KCT_ZINST(TS, TD) template hipError_t launch_zfast_copy<TS, TD>(const GeoDev &, const TS *, TD *, hipStream_t);
+KCT_ZINST(float, float)
+KCT_ZINST(bf16, bf16)
+KCT_ZINST(_Float16, _Float16)
 
 }  // namespace kct

@@ -1,0 +1,174 @@
+"""Storage precision form: volumes, projections and solver work vectors stored
+in BF16 or FP16 with single-precision ray accumulation and double-precision
+solver scalars, against the FP64 oracle.
+
+Projector tolerances follow from the arithmetic.  The oracle is given the
+storage-rounded input, so the only differences are the single-precision
+accumulation (relative 1e-5, the FP32 bound) and the final rounding of every
+output element to the storage type: round-to-nearest changes an element by at
+most 2^-9 (BF16, 8 significand bits) or 2^-11 (FP16, 11 bits) of its value,
+which bounds the relative L2 error of the whole vector by the same amount.
+
+Solver tolerances are empirical: every iteration rounds r, d, p and e (CGLS)
+or u, v and w (LSQR) to the storage type, and those perturbations propagate
+through the recurrences; the bound used is about four times the error
+measured on the c1 problem, and the FP32 form is checked at the same time.
+"""
+import numpy as np
+import pytest
+
+import kct_inputs as ki
+import oracle
+from tests.gpu_util import dev, geometry, rel, say, to_np, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+STORE_BOUND = {"bf16": 2.0 ** -9, "f16": 2.0 ** -11}
+ACC_TOL = 1e-5
+
+
+def _tdt(name):
+    torch = torch_mod()
+    return {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[name]
+
+
+def _store(a, name):
+    """Round a float32 array to the storage type (torch's round-to-nearest-even) and back."""
+    torch = torch_mod()
+    t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(_tdt(name))
+    return t.float().numpy().astype(np.float64)
+
+
+def _dev(a, name):
+    torch = torch_mod()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev()).to(_tdt(name))
+
+
+CASES = ["offcenter", "odd", "c1"]
+
+
+def _geom(case):
+    return ki.config("c1") if case == "c1" else ki.t16(case)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("case", CASES)
+def test_forward_storage(case, dt):
+    import paper_2110_13526_amd as kct
+    g = _geom(case)
+    say(f"[precision] forward {case} {dt}")
+    G = geometry(g)
+    x = _store(ki.phantom(g, 10, 7), dt)
+    ref = oracle.project(g, x)
+    tol = STORE_BOUND[dt] + ACC_TOL
+    for tc in (True, False):
+        b = kct.project(G, _dev(x, dt), transposed_copy=tc)
+        assert b.dtype == _tdt(dt)
+        err = rel(to_np(b), ref)
+        say(f"  transposed_copy={tc}: rel {err:.3e} (bound {tol:.3e})")
+        assert err < tol, err
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("case", CASES)
+def test_backward_storage(case, dt):
+    import paper_2110_13526_amd as kct
+    g = _geom(case)
+    say(f"[precision] backward {case} {dt}")
+    G = geometry(g)
+    y = _store(np.abs(ki.random_projections(g, 11)), dt)
+    ref = oracle.backproject(g, y)
+    r = kct.backproject(G, _dev(y, dt))
+    assert r.dtype == _tdt(dt)
+    err = rel(to_np(r), ref)
+    tol = STORE_BOUND[dt] + ACC_TOL
+    say(f"  rel {err:.3e} (bound {tol:.3e})")
+    assert err < tol, err
+
+
+@pytest.fixture(scope="module")
+def c1_problem():
+    g = ki.config("c1")
+    x_true = ki.phantom(g, ki.N_ELLIPSOIDS["c1"], ki.SEEDS["c1"])
+    b = oracle.project(g, x_true.astype(np.float64))
+    b = ki.gaussian_noise(b, 0.005, ki.SEEDS["c1"] + 1_000_000).astype(np.float32)
+    return g, geometry(g), x_true, b
+
+
+SOLVE_TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 4e-3}
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("solver", ["cgls", "lsqr"])
+def test_solver_storage_c1(c1_problem, solver, dt):
+    """K = 10 iterations with 16-bit work vectors against the FP64 oracle run on
+    the same storage-rounded b; the iterate x stays single precision."""
+    import paper_2110_13526_amd as kct
+    g, G, x_true, b = c1_problem
+    bs = _store(b, dt)
+    K = 10
+    ref = (oracle.cgls if solver == "cgls" else oracle.lsqr)(g, bs, K)
+    x, info = getattr(kct, solver)(G, _dev(bs, dt), K, history=True)
+    assert x.dtype == torch_mod().float32
+    err = rel(to_np(x), ref.x)
+    herr = float(np.max(np.abs(to_np(info.history) - ref.history) / ref.history))
+    say(f"[precision] {solver} c1 {dt}: x rel {err:.3e}, history max rel {herr:.3e}, "
+        f"err vs x_true {rel(to_np(x), x_true):.4f} (oracle {rel(ref.x, x_true):.4f})")
+    assert info.iterations == K
+    assert err < SOLVE_TOL[dt], err
+    assert herr < SOLVE_TOL[dt], herr
+
+
+def test_f16_solver_range_needs_scaling(c1_problem):
+    """Unscaled, the first CGLS direction of this problem, p = A A^T b, leaves
+    the FP16 range (largest finite value 65504).  With the storage scales the
+    FP16 solve stays finite and tracks the FP32 one."""
+    import paper_2110_13526_amd as kct
+    g, G, x_true, b = c1_problem
+    p = kct.project(G, kct.backproject(G, _dev(b, "f32")))
+    assert float(p.abs().max()) > 65504.0
+    x32, i32 = kct.cgls(G, _dev(b, "f32"), 10)
+    x16, i16 = kct.cgls(G, _dev(b, "f16"), 10)
+    assert np.isfinite(i16.nb)
+    assert rel(to_np(x16), to_np(x32)) < SOLVE_TOL["f16"]
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("KCT_PRECISION_REPORT"),
+                    reason="report run (set KCT_PRECISION_REPORT=1): the FP64 oracle needs minutes for "
+                           "30 CGLS iterations at 128^3 x 720 views")
+def test_precision_report_c3down():
+    """The 512^3 x 720-view problem downsampled to 128^3 (1 mm voxels, 154 x 120
+    detector of 2.4 mm pixels): CGLS, 30 iterations, x0 = 0, with FP32, BF16 and
+    FP16 storage (b included); relative L2 error of each against the FP64
+    oracle run on the FP32 data, and against the phantom."""
+    import json
+    import time
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g = ki.config("c3down")
+    G = geometry(g)
+    x_true = ki.phantom(g, ki.N_ELLIPSOIDS["c3down"], ki.SEEDS["c3down"])
+    b = oracle.project(g, x_true.astype(np.float64))
+    b = ki.poisson_log_noise(b, 1e4, ki.SEEDS["c3down"] + 1_000_000).astype(np.float32)
+    K = 30
+    t = time.perf_counter()
+    ref = oracle.cgls(g, b.astype(np.float64), K)
+    t_ref = time.perf_counter() - t
+    say(f"[precision] c3down oracle: {t_ref:.1f} s")
+    report = {}
+    for dt in ("f32", "bf16", "f16"):
+        bd = _dev(b, dt)
+        kct.cgls(G, bd, K)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = kct.cgls(G, bd, K)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t
+        xn = to_np(x)
+        report[dt] = {"rel_l2_vs_fp64_oracle": rel(xn, ref.x), "rel_l2_vs_phantom": rel(xn, x_true),
+                      "oracle_rel_l2_vs_phantom": rel(ref.x, x_true), "discrepancy": info.nb / info.nb0,
+                      "gpu_s": t_gpu}
+        say(f"[precision] c3down {dt}: {json.dumps(report[dt])}")
+    assert report["f32"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["f32"]
+    assert report["bf16"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["bf16"]
+    assert report["f16"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["f16"]
