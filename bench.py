@@ -18,6 +18,7 @@ Besides the JSON fields of the benchmark contract the line carries
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -30,6 +31,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# Files each projector kernel is compiled from; the measured-traffic record in
+# profiles/ is valid only for the sources it was taken with.
+KERNEL_SOURCES = {
+    "forward": ("projector.hip", "kct_ray.h", "kct_weights.h", "kct_internal.h"),
+    "backward": ("backproject.hip", "kct_gather.h", "kct_weights.h", "kct_internal.h"),
+}
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "projector_c3_hbm_counters.json")
+
+
+def kernel_source_hash(kind):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, "paper_2110_13526_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic_bytes(kind, workload, dtype):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated against a copy
+    of known size) from the committed counter record, or None when there is no
+    record for this kernel, workload and storage type, or the kernel's sources
+    changed since it was taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(f"{kind}_{dtype}")
+    if not ent or rec.get("workload") != workload or ent.get("source_sha256") != kernel_source_hash(kind):
+        return None
+    cal = rec["calibration"]
+    return (ent["fetch_kib"] * cal["fetch_factor"] + ent["write_kib"] * cal["write_factor"]) * 1024.0
 
 
 def log(*a):
@@ -45,8 +79,12 @@ def main():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-views", type=int, default=8, help="views in the CPU-oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=96, help="views in the CPU-oracle sample")
     ap.add_argument("--nnz-views", type=int, default=90, help="views sampled to count nonzeros")
+    ap.add_argument("--no-precision", action="store_true", help="skip the BF16 / FP16 comparison solves")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="profiling pass: one forward, one backward and one 1 GiB device copy (the "
+                         "calibration of the HBM byte counters), nothing timed")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -73,6 +111,19 @@ def main():
     bn = ki.poisson_log_noise(b32.cpu().numpy(), 1e4, ki.SEEDS[args.config] + 1_000_000)
     b = torch.from_numpy(bn).to(dev).to(tdt)
     del b32, bn
+    if args.kernels_only:
+        xin = xt.to(tdt)
+        pbuf = torch.empty(g.proj_shape, dtype=tdt, device=dev)
+        vbuf = torch.empty(g.vol_shape, dtype=tdt, device=dev)
+        pws = torch.empty(G.project_workspace_bytes(tdt), dtype=torch.uint8, device=dev)
+        kct.project(G, xin, out=pbuf, workspace=pws)
+        kct.backproject(G, b, out=vbuf)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB read, 1 GiB written
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] kernels-only pass done: forward, backward, 1 GiB copy")
+        return
     ws = torch.empty(G.solver_workspace_bytes(tdt, "cgls"), dtype=torch.uint8, device=dev)
     out = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)  # the iterate is always FP32
     torch.cuda.synchronize()
@@ -126,8 +177,13 @@ def main():
     bwd_bytes = nnz * s_bytes + g.n_vox * s_bytes
     dominant = "backward" if t_bwd >= t_fwd else "forward"
     ach = (bwd_bytes / t_bwd if dominant == "backward" else fwd_bytes / t_fwd) / 1e9
+    t_dom = t_bwd if dominant == "backward" else t_fwd
+    tb = measured_traffic_bytes(dominant, args.config, args.dtype)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dominant,
+                "frac": round(ach / HBM_PEAK_GBS, 4),
+                "traffic": None if tb is None else round(tb / t_dom / 1e9, 1),
+                "traffic_bytes_per_launch": None if tb is None else float(f"{tb:.4g}"),
+                "kernel": dominant,
                 "forward_ms": round(t_fwd * 1e3, 3), "backward_ms": round(t_bwd * 1e3, 3),
                 "forward_GBs": round(fwd_bytes / t_fwd / 1e9, 1), "backward_GBs": round(bwd_bytes / t_bwd / 1e9, 1),
                 "nnz_per_application": float(f"{nnz:.4g}")}
@@ -151,6 +207,33 @@ def main():
                          f"{t_a + t_at:.1f} s, scaled by {g.n_views / subc.n_views:g}; vector updates excluded"}
         log(f"[bench] cpu oracle sample: A {t_a:.2f} s, A^T {t_at:.2f} s on {subc.n_views} views")
 
+    # --- the same solve with 16-bit storage (BF16 / FP16 work vectors and b, FP32 iterate)
+    precision = None
+    if not args.no_precision:
+        precision = {args.dtype: {"iters_per_s": round(value, 4), "rel_error_vs_x_true": round(rec_err, 6),
+                                  "relative_discrepancy": round(e_final, 6)}}
+        for name, odt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
+            if name == args.dtype:
+                continue
+            bo = b.float().to(odt)
+            wso = torch.empty(G.solver_workspace_bytes(odt, "cgls"), dtype=torch.uint8, device=dev)
+            kct.cgls(G, bo, 2, workspace=wso, out=out)  # warm-up of this storage type's kernels
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = kct.cgls(G, bo, args.iters, workspace=wso, out=out)
+            torch.cuda.synchronize()
+            dto = time.perf_counter() - t
+            err_o = (torch.linalg.vector_norm((out - xt).double()) / torch.linalg.vector_norm(xt.double())).item()
+            precision[name] = {"iters_per_s": round(info.iterations / dto, 4), "rel_error_vs_x_true": round(err_o, 6),
+                               "relative_discrepancy": round(info.nb / info.nb0, 6)}
+            log(f"[bench] {name}: {precision[name]}")
+            del wso, bo
+        ref = precision["f32"]
+        for name, r in precision.items():
+            r["speedup_vs_f32"] = round(r["iters_per_s"] / ref["iters_per_s"], 4)
+            r["error_ratio_vs_f32"] = round(r["rel_error_vs_x_true"] / ref["rel_error_vs_x_true"], 6)
+            r["equal_error"] = abs(r["error_ratio_vs_f32"] - 1.0) <= 0.01
+
     line = {
         "metric": "CGLS iters/s + GB/s vs HBM roofline, 512^3x720 views, BF16 vs FP32 at equal err",
         "value": round(value, 4), "unit": "CGLS iters/s", "n_gpus": 1, "steps": args.steps,
@@ -161,6 +244,7 @@ def main():
                    "iterations_per_step": args.iters, "relative_discrepancy": round(e_final, 6),
                    "rel_error_vs_x_true": round(rec_err, 6), "parallelism": "single GPU"},
         "roofline": roofline,
+        "precision": precision,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

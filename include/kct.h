@@ -26,9 +26,10 @@
  *
  * Memory layout (dense, no padding): volume x[iz][iy][ix] (ix fastest),
  * projections b[k][iv][iu] (iu fastest).  Storage type is chosen per call
- * (kct_dtype); ray and voxel accumulation is single precision, solver scalars
- * (norms, step lengths, Givens rotations) are double precision on the device,
- * and the solvers' iterate x is always single precision.
+ * (kct_dtype); ray and voxel accumulation is single precision (double for
+ * KCT_F64), solver scalars (norms, step lengths, Givens rotations) are double
+ * precision on the device, and the solvers' iterate x is always single
+ * precision.
  *
  * Conventions for every function below:
  *  - Data pointers are DEVICE pointers of the current HIP device unless marked
@@ -64,8 +65,11 @@ typedef enum {
     KCT_ERR_NUMERIC = 5      /* a solver norm became NaN or Inf                     */
 } kct_status;
 
-/* Storage type of volumes, projections and workspace vectors. */
-typedef enum { KCT_F32 = 0, KCT_BF16 = 1, KCT_F16 = 2 } kct_dtype;
+/* Storage type of volumes, projections and workspace vectors.  The weights
+ * are single precision in every case; F32, BF16 and F16 accumulate in single
+ * precision, F64 in double (F64 is for the projector pair only: it evaluates
+ * the same matrix to double-precision rounding, e.g. for gradient checks). */
+typedef enum { KCT_F32 = 0, KCT_BF16 = 1, KCT_F16 = 2, KCT_F64 = 3 } kct_dtype;
 
 /* Voxel grid: counts, voxel size [mm] and the volume centre [mm] (off-centre
  * reconstruction, Section 3). */
@@ -125,12 +129,27 @@ kct_status kct_project(kct_geometry g, kct_dtype dtype, const void *x, void *b, 
  * atomics, deterministic.  Errors: INVALID_ARG, UNSUPPORTED, HIP. */
 kct_status kct_backproject(kct_geometry g, kct_dtype dtype, const void *b, void *x, hipStream_t stream);
 
-/* Solver options (Algorithm 1 inputs besides b and x0). */
+/* Solver options (Algorithm 1 inputs besides b and x0, and the variants the
+ * paper describes in Sections 3, 5 and 7).  Zero-initialise the struct for plain CGLS /
+ * LSQR. */
 typedef struct {
     int32_t max_iter;   /* K >= 0; K = 0 returns x0 unchanged                           */
     double err_tol;     /* ERR >= 0: stop once NB <= ERR * NB0 (NB0 = |b|, Eq. 3)        */
     int32_t x0_is_zero; /* nonzero: x is not read, the solve starts from x0 = 0          */
     double *history;    /* (device, optional) max_iter doubles: NB_i / NB0 per iteration  */
+    double tikhonov;    /* lambda >= 0: minimise |b - A x|^2 + lambda^2 |x|^2 (the Tikhonov
+                           / L2 regularisation of Sections 3 and 7).  CGLS runs on the
+                           stacked system [A; lambda I]; LSQR uses Paige & Saunders'
+                           damping and then needs x0 = 0.  With lambda > 0, LSQR's NB is
+                           the norm of the stacked residual [b - A x; -lambda x]; CGLS's
+                           NB stays |b - A x|.                                             */
+    int32_t jacobi;     /* CGLS only, nonzero: Jacobi preconditioning (Sections 3, 5): CGLS on
+                           A M with M = diag(A^T A)^(-1/2) (0 where the diagonal is 0),
+                           x = M z.  Needs the workspace of KCT_SOLVER_CGLS |
+                           KCT_SOLVER_WITH_JACOBI; not with tikhonov > 0 or F16 storage. */
+    int32_t recompute_every; /* CGLS only, k > 0: after every k-th iteration e = b - A x is
+                           recomputed instead of updated (Section 5 discusses the drift
+                           of the updated discrepancy); costs one more A per k iterations. */
 } kct_solve_opts;
 
 /* Stop reasons. */
@@ -145,12 +164,14 @@ typedef struct {
     int32_t stop_reason; /* KCT_STOP_*                                          */
 } kct_solve_info;
 
-enum { KCT_SOLVER_CGLS = 0, KCT_SOLVER_LSQR = 1 };
+enum { KCT_SOLVER_CGLS = 0, KCT_SOLVER_LSQR = 1, KCT_SOLVER_WITH_JACOBI = 0x100 };
 
-/* Workspace bytes for a solver.  CGLS holds d, r and a z-fastest copy of d
- * (volumes) and e, p (projections): the paper's three volumes and three
+/* Workspace bytes for a solver (KCT_SOLVER_CGLS or KCT_SOLVER_LSQR, for CGLS
+ * optionally | KCT_SOLVER_WITH_JACOBI).  CGLS holds d, r and a z-fastest copy
+ * of d (volumes) and e, p (projections): the paper's three volumes and three
  * projection vectors with x and b (Section 5) plus the copy, and a small block
- * of double-precision scalars and reduction partials.  LSQR holds v, w and a
+ * of double-precision scalars and reduction partials; with Jacobi one more
+ * single-precision volume (the preconditioner).  LSQR holds v, w and a
  * z-fastest copy of v (volumes) and u (projections). */
 kct_status kct_solver_workspace_size(kct_geometry g, kct_dtype dtype, int32_t solver, size_t *bytes);
 
@@ -172,6 +193,57 @@ kct_status kct_cgls_solve(kct_geometry g, kct_dtype dtype, const void *b, void *
  * Same arguments, ownership and errors as kct_cgls_solve. */
 kct_status kct_lsqr_solve(kct_geometry g, kct_dtype dtype, const void *b, void *x, const kct_solve_opts *opts,
                           void *ws, size_t ws_bytes, kct_solve_info *info, hipStream_t stream);
+
+/* diag(A^T A): out_j = sum_i w_ij^2, the squared column norms of A (the
+ * diagonal that Jacobi preconditioning inverts, Section 5), computed by the
+ * backprojector's gather with squared weights.  out: n_vox floats (device),
+ * volume layout.  Errors: INVALID_ARG, HIP. */
+kct_status kct_diag_normal(kct_geometry g, float *out, hipStream_t stream);
+
+/* ---------------------------------------------------------------- batched CGLS
+ * Many independent reconstructions, each with its own geometry (volume,
+ * detector, views, distances), solved together: every step of Algorithm 1 is
+ * one kernel launch that covers all instances, each instance keeps its own
+ * double-precision scalars, partial sums and stop flag (so an instance gets
+ * exactly the result of its own kct_cgls_solve when both use the same forward
+ * variant), and the steps of one iteration are recorded once as a HIP graph and
+ * replayed.  FP32 storage. */
+typedef struct kct_batch_s *kct_batch;
+
+/* geoms: count geometry handles (host array), all created on the current
+ * device; they must outlive the batch.  The batch owns one stream of its own
+ * (default priority) for graph capture.  Errors: INVALID_ARG, HIP. */
+kct_status kct_batch_create(const kct_geometry *geoms, int32_t count, kct_batch *out);
+
+/* Synchronises the batch's stream and frees it (NULL is ignored). */
+void kct_batch_destroy(kct_batch b);
+
+/* Bytes of workspace of kct_batch_cgls_solve and kct_batch_tune: a small table
+ * plus, per instance, CGLS's d, its z-fastest copy, r (volumes), e, p
+ * (projections), scalars and partial sums. */
+kct_status kct_batch_workspace_size(kct_batch b, size_t *bytes);
+
+/* Autotuner: for each instance, time its forward projection with one and with
+ * two detector rows per lane (3 launches each after a warm-up, HIP events) and
+ * keep the faster for the batch's solves.  cache_path (host, optional): a text
+ * file of "<sizes> <rows per lane>" lines; instances whose sizes are listed are
+ * not timed, new choices are appended.  ws is scratch (kct_batch_workspace_size
+ * bytes, contents overwritten).  Synchronous.  Errors: INVALID_ARG, WORKSPACE,
+ * HIP. */
+kct_status kct_batch_tune(kct_batch b, void *ws, size_t ws_bytes, const char *cache_path, hipStream_t stream);
+
+/* For every instance i: x_i := K iterations of CGLS (Algorithm 1) on b_i from
+ * x0 = 0.  opts: max_iter and err_tol apply to every instance; x0_is_zero must
+ * be nonzero and the other fields zero.  bs, xs: host arrays of count device
+ * pointers (n_rays_i and n_vox_i floats, 16-byte aligned).  use_graph nonzero:
+ * iterations 2..K replay one recorded HIP graph (the same results as plain
+ * launches).  ws: 256-byte aligned.  infos: host array of count results.  The
+ * solve is ordered after earlier work on `stream` and synchronises before it
+ * returns.  Errors: INVALID_ARG, WORKSPACE, HIP; KCT_ERR_NUMERIC if NB became
+ * NaN/Inf in some instance (infos still filled). */
+kct_status kct_batch_cgls_solve(kct_batch b, const float *const *bs, float *const *xs, const kct_solve_opts *opts,
+                                int32_t use_graph, void *ws, size_t ws_bytes, kct_solve_info *infos,
+                                hipStream_t stream);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *kct_last_error(void);

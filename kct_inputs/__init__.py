@@ -137,6 +137,30 @@ def config(name: str) -> ConeGeometry:
     raise ValueError(name)
 
 
+def batch_instance(i: int, scale: float = 1.0) -> ConeGeometry:
+    """Instance i of the batched workload (48 uneven reconstructions), drawn
+    from default_rng(4000 + i) in this order: volume side n in {64, 96, 128, 192},
+    views in 60..360, square detector side in 96..288 pixels of 1 mm, SID in
+    [400, 700] mm, SDD in [800, 1400] mm (at least SID + 100).  The voxel size
+    makes the volume fill 95 % of the cylinder the detector sees:
+    v = 0.95 * 2 * SID * sin(atan(side / (2 SDD))) / n.  ``scale`` shrinks n,
+    views and side for small test batches (geometry ratios kept)."""
+    rng = np.random.default_rng(4000 + i)
+    n = int(rng.choice([64, 96, 128, 192]))
+    views = int(rng.integers(60, 361))
+    side = int(rng.integers(96, 289))
+    sid = float(rng.uniform(400.0, 700.0))
+    sdd = float(rng.uniform(800.0, 1400.0))
+    sdd = max(sdd, sid + 100.0)
+    if scale != 1.0:
+        n = max(8, int(round(n * scale)))
+        views = max(4, int(round(views * scale)))
+        side = max(8, int(round(side * scale)))
+    du = 1.0 / scale
+    vox = 0.95 * 2.0 * sid * math.sin(math.atan(side * du / (2.0 * sdd))) / n
+    return ConeGeometry(n, n, n, vox, vox, vox, views, side, side, du, du, sid=sid, sdd=sdd)
+
+
 SEEDS = {"c1": 101, "c2": 202, "c3": 303, "c3down": 303, "c5": 5000, "fd24": 5000}
 N_ELLIPSOIDS = {"c1": 10, "c2": 20, "c3": 20, "c3down": 20, "c5": 10, "fd24": 10}
 

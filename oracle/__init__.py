@@ -68,6 +68,16 @@ def lib():
         L.oracle_lsqr.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                         dp, dp, dp, ip]
         L.oracle_lsqr.restype = ctypes.c_int
+        L.oracle_cgls_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
+        L.oracle_cgls_ex.restype = ctypes.c_int
+        L.oracle_lsqr_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                           ctypes.c_double, dp, dp, dp, ip]
+        L.oracle_lsqr_ex.restype = ctypes.c_int
+        L.oracle_diag_normal.argtypes = geo + [dp]
+        L.oracle_diag_normal.restype = None
+        L.oracle_cgls_jacobi.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
+        L.oracle_cgls_jacobi.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -172,31 +182,58 @@ class SolveResult:
         return f"SolveResult(iterations={self.iterations}, nb={self.nb:.6g}, stop={self.stop_reason})"
 
 
-def cgls(g, b, K, x0=None, err=0.0, literal_update=False):
-    """Algorithm 1 (CGLS with delayed residual) in FP64."""
+def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0):
+    """Algorithm 1 (CGLS with delayed residual) in FP64.
+
+    tikhonov = lambda adds lambda^2 |x|^2 to the objective (CGLS on [A; lambda I]);
+    recompute_every = k > 0 recomputes e = b - A x after every k-th iteration."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
     hist = np.zeros(max(K, 1), dtype=np.float64)
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
-    stop = lib().oracle_cgls(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                             int(bool(literal_update)), _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0),
-                             ctypes.byref(it))
+    stop = lib().oracle_cgls_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
+                                int(bool(literal_update)), float(tikhonov), int(recompute_every), _ptr(hist),
+                                ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 
 
-def lsqr(g, b, K, x0=None, err=0.0):
-    """LSQR (Paige & Saunders) in FP64, iterations aligned with CGLS."""
+def lsqr(g, b, K, x0=None, err=0.0, damp=0.0):
+    """LSQR (Paige & Saunders) in FP64, iterations aligned with CGLS.
+
+    damp = lambda > 0 solves min |b - A x|^2 + lambda^2 |x - x0|^2."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
     hist = np.zeros(max(K, 1), dtype=np.float64)
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
-    stop = lib().oracle_lsqr(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                             _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
+    stop = lib().oracle_lsqr_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
+                                float(damp), _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
+    return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
+                       hist[: it.value].copy())
+
+
+def diag_normal(g):
+    """diag(A^T A) = sum_i w_ij^2 per voxel, FP64."""
+    gt = _geo(g)
+    out = np.zeros(g.nx * g.ny * g.nz)
+    lib().oracle_diag_normal(*_gargs(gt), _ptr(out))
+    return out.reshape(g.nz, g.ny, g.nx)
+
+
+def cgls_jacobi(g, b, K, x0=None, err=0.0):
+    """Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)) in FP64."""
+    gt = _geo(g)
+    b = _proj(g, b)
+    x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
+    hist = np.zeros(max(K, 1), dtype=np.float64)
+    nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
+    it = ctypes.c_int(0)
+    stop = lib().oracle_cgls_jacobi(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
+                                    _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 

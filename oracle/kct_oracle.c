@@ -31,6 +31,11 @@
  *   LSQR   -- named in Section 2 (Paige & Saunders 1982); not printed in the
  *             paper, so the published Golub-Kahan bidiagonalisation + Givens
  *             form is followed, with x0 entering through u = b - A x0.
+ *   Variants named in Sections 3, 5 and 7: the Tikhonov (L2) term
+ *             lambda^2 |x|^2 (CGLS on the stacked system [A; lambda I]; LSQR
+ *             with Paige & Saunders' damping), the diagonal of A^T A and
+ *             Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)),
+ *             and CGLS with the discrepancy recomputed every k iterations.
  *
  * Geometry convention (the paper gives only SID, SDD, pixel size and the number
  * of angles, Section 4): right-handed world frame in mm, rotation axis +z,
@@ -312,6 +317,40 @@ void oracle_backproject(const int32_t *dims, const double *par, const double *an
     }
 }
 
+/* diag(A^T A)_j = sum_i w_ij^2 (the squared column norms of A; the diagonal of
+ * the normal equations that Jacobi preconditioning uses, Section 5).  Same
+ * slab-parallel scatter as the backprojection, with squared weights. */
+void oracle_diag_normal(const int32_t *dims, const double *par, const double *angles, double *out)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    memset(out, 0, sizeof(double) * (size_t)nvox);
+    int64_t nrays = (int64_t)g.nviews * g.nv * g.nu;
+    int nslab = 2 * omp_get_max_threads();
+    if (nslab > g.nz) nslab = g.nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int sl = 0; sl < nslab; ++sl) {
+        int zlo = (int)((int64_t)g.nz * sl / nslab);
+        int zhi = (int)((int64_t)g.nz * (sl + 1) / nslab);
+        int cap = og_cap(&g);
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *w = (double *)malloc(sizeof(double) * (size_t)cap);
+        og_scratch sc = og_scratch_new(&g);
+        for (int64_t ri = 0; ri < nrays; ++ri) {
+            int k = (int)(ri / ((int64_t)g.nv * g.nu));
+            int iv = (int)((ri / g.nu) % g.nv);
+            int iu = (int)(ri % g.nu);
+            double s[3], q[3];
+            og_ray(&g, k, iv, iu, s, q);
+            int n = og_trace(&g, &sc, s, q, zlo, zhi, idx, w);
+            for (int j = 0; j < n; ++j) out[idx[j]] += w[j] * w[j];
+        }
+        free(idx);
+        free(w);
+        og_scratch_free(&sc);
+    }
+}
+
 /* Length of the segment s->q inside the half-open box [b0, b1) (slab method). */
 static double og_seg_box(const double s[3], const double q[3], const double b0[3], const double b1[3])
 {
@@ -469,11 +508,33 @@ enum { OG_STOP_MAXITER = 0, OG_STOP_TOL = 1, OG_STOP_BREAKDOWN = 2, OG_STOP_NUME
  * NR2 = 0 or NP2 = 0 is a breakdown that stops with the current x.
  * literal_update = 1 uses the printed direction update d = d + beta r.
  */
-int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
-                const double *b, double *x, int K, double err, int x0_is_zero,
-                int literal_update, double *history, double *out_nb, double *out_nb0,
-                int *out_iters)
+/* e = e - alpha p (the update of Algorithm 1), or e = b - A x when recompute. */
+static void og_cgls_discrepancy(const int32_t *dims, const double *par, const double *angles, const double *b,
+                                const double *x, double *e, double *p, double alpha, int64_t m, int recompute)
 {
+    if (recompute) {
+        oracle_project(dims, par, angles, x, p);
+        for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
+    } else {
+        for (int64_t t = 0; t < m; ++t) e[t] -= alpha * p[t];
+    }
+}
+
+/*
+ * CGLS with the Tikhonov term of the paper's conclusions, lambda^2 |x|^2 (CGLS
+ * on the stacked system [A; lambda I] x = [b; 0]): the residual of the lower
+ * block is -lambda x, so r = A^T e - lambda^2 x and |[A; lambda I] d|^2 =
+ * |A d|^2 + lambda^2 |d|^2; e = b - A x stays the data discrepancy whose norm
+ * is NB.  recompute_every = k > 0 replaces the update e -= alpha p by
+ * e = b - A x after every k-th iteration (the periodic recomputation of the
+ * discrepancy that Section 5 discusses).  lambda = 0, k = 0 is Algorithm 1.
+ */
+int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
+                   const double *b, double *x, int K, double err, int x0_is_zero,
+                   int literal_update, double lambda, int recompute_every, double *history,
+                   double *out_nb, double *out_nb0, int *out_iters)
+{
+    const double l2 = lambda * lambda;
     og_t g = og_make(dims, par, angles);
     int64_t n = (int64_t)g.nx * g.ny * g.nz;
     int64_t m = (int64_t)g.nviews * g.nv * g.nu;
@@ -492,24 +553,28 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
     else oracle_project(dims, par, angles, x, p);
     for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
     NB = sqrt(og_dot(e, e, m));
-    /* r = A^T e ; d = r ; NR2_old = |r|^2 */
+    /* r = A^T e - lambda^2 x ; d = r ; NR2_old = |r|^2 */
     oracle_backproject(dims, par, angles, e, r);
+    if (l2 != 0.0)
+        for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
     memcpy(d, r, sizeof(double) * (size_t)n);
     double NR2_old = og_dot(r, r, n);
     if (NR2_old == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
-    /* p = A d ; NP2 ; alpha ; x += alpha d ; e -= alpha p ; NB */
+    /* p = A d ; NP2 = |p|^2 + lambda^2 |d|^2 ; alpha ; x += alpha d ; e -= alpha p ; NB */
     oracle_project(dims, par, angles, d, p);
-    double NP2 = og_dot(p, p, m);
+    double NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
     if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     double alpha = NR2_old / NP2;
     for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
-    for (int64_t t = 0; t < m; ++t) e[t] -= alpha * p[t];
-    NB = sqrt(og_dot(e, e, m));
     i = 1;
+    og_cgls_discrepancy(dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+    NB = sqrt(og_dot(e, e, m));
     if (history) history[0] = NB0 > 0 ? NB / NB0 : 0.0;
     if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
     while (NB > err * NB0 && i < K) {
         oracle_backproject(dims, par, angles, e, r);
+        if (l2 != 0.0)
+            for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
         double NR2_now = og_dot(r, r, n);
         if (NR2_now == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         double beta = NR2_now / NR2_old;
@@ -519,13 +584,13 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
             for (int64_t t = 0; t < n; ++t) d[t] = r[t] + beta * d[t];
         NR2_old = NR2_now;
         oracle_project(dims, par, angles, d, p);
-        NP2 = og_dot(p, p, m);
+        NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
         if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         alpha = NR2_old / NP2;
         for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
-        for (int64_t t = 0; t < m; ++t) e[t] -= alpha * p[t];
-        NB = sqrt(og_dot(e, e, m));
         i = i + 1;
+        og_cgls_discrepancy(dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+        NB = sqrt(og_dot(e, e, m));
         if (history) history[i - 1] = NB0 > 0 ? NB / NB0 : 0.0;
         if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
     }
@@ -540,6 +605,81 @@ done:
 }
 
 /*
+ * Jacobi-preconditioned CGLS (Section 5): Algorithm 1 applied to the operator
+ * A M, M = diag(A^T A)^(-1/2) (0 where the diagonal is 0), for the correction
+ * z of x = x0 + M z, starting from z = 0.  Products: (A M) d = A (M d),
+ * (A M)^T e = M (A^T e).  NB = |b - A x| as in Algorithm 1.
+ */
+int oracle_cgls_jacobi(const int32_t *dims, const double *par, const double *angles,
+                       const double *b, double *x, int K, double err, int x0_is_zero, double *history,
+                       double *out_nb, double *out_nb0, int *out_iters)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t n = (int64_t)g.nx * g.ny * g.nz;
+    int64_t m = (int64_t)g.nviews * g.nv * g.nu;
+    double *M = (double *)calloc((size_t)n, sizeof(double));
+    double *d = (double *)calloc((size_t)n, sizeof(double));
+    double *r = (double *)calloc((size_t)n, sizeof(double));
+    double *md = (double *)calloc((size_t)n, sizeof(double));
+    double *e = (double *)calloc((size_t)m, sizeof(double));
+    double *p = (double *)calloc((size_t)m, sizeof(double));
+    int stop = OG_STOP_MAXITER, i = 0;
+    double NB0 = sqrt(og_dot(b, b, m)), NB = NB0;
+    if (K <= 0) goto done;
+    oracle_diag_normal(dims, par, angles, M);
+    for (int64_t t = 0; t < n; ++t) M[t] = M[t] > 0.0 ? 1.0 / sqrt(M[t]) : 0.0;
+    if (x0_is_zero) memset(x, 0, sizeof(double) * (size_t)n);
+    /* e = b - A x0 */
+    if (x0_is_zero) memset(p, 0, sizeof(double) * (size_t)m);
+    else oracle_project(dims, par, angles, x, p);
+    for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
+    NB = sqrt(og_dot(e, e, m));
+    double NR2_old = 0.0;
+    while (i < K) {
+        /* r = (A M)^T e */
+        oracle_backproject(dims, par, angles, e, r);
+        for (int64_t t = 0; t < n; ++t) r[t] *= M[t];
+        double NR2 = og_dot(r, r, n);
+        if (NR2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
+        if (i == 0) memcpy(d, r, sizeof(double) * (size_t)n);
+        else {
+            double beta = NR2 / NR2_old;
+            for (int64_t t = 0; t < n; ++t) d[t] = r[t] + beta * d[t];
+        }
+        NR2_old = NR2;
+        /* p = (A M) d; alpha = NR2 / |p|^2; z += alpha d, i.e. x += alpha M d; e -= alpha p */
+        for (int64_t t = 0; t < n; ++t) md[t] = M[t] * d[t];
+        oracle_project(dims, par, angles, md, p);
+        double NP2 = og_dot(p, p, m);
+        if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
+        double alpha = NR2 / NP2;
+        for (int64_t t = 0; t < n; ++t) x[t] += alpha * md[t];
+        for (int64_t t = 0; t < m; ++t) e[t] -= alpha * p[t];
+        NB = sqrt(og_dot(e, e, m));
+        i = i + 1;
+        if (history) history[i - 1] = NB0 > 0 ? NB / NB0 : 0.0;
+        if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
+        if (!(NB > err * NB0)) { stop = i >= K ? OG_STOP_MAXITER : OG_STOP_TOL; goto done; }
+    }
+    stop = OG_STOP_MAXITER;
+done:
+    if (out_nb) *out_nb = NB;
+    if (out_nb0) *out_nb0 = NB0;
+    if (out_iters) *out_iters = i;
+    free(M); free(d); free(r); free(md); free(e); free(p);
+    return stop;
+}
+
+int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
+                const double *b, double *x, int K, double err, int x0_is_zero,
+                int literal_update, double *history, double *out_nb, double *out_nb0,
+                int *out_iters)
+{
+    return oracle_cgls_ex(dims, par, angles, b, x, K, err, x0_is_zero, literal_update, 0.0, 0, history, out_nb,
+                          out_nb0, out_iters);
+}
+
+/*
  * LSQR (Paige & Saunders 1982), the method the paper pairs with CGLS.
  *   beta u = b - A x0, alpha v = A^T u, w = v, phibar = beta, rhobar = alpha;
  *   per iteration: beta u = A v - alpha u; alpha v = A^T u - beta v;
@@ -550,9 +690,17 @@ done:
  * the last iteration is not needed for x_K and is skipped, so K iterations cost
  * K products with A and K with A^T (one more A when x0 != 0), as for CGLS.
  */
-int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
-                const double *b, double *x, int K, double err, int x0_is_zero,
-                double *history, double *out_nb, double *out_nb0, int *out_iters)
+/*
+ * With damp = lambda > 0 the method solves min |b - A x|^2 + lambda^2 |x - x0|^2
+ * (Paige & Saunders' damped least squares): before each rotation rhobar is
+ * rotated against lambda, rhobar1 = hypot(rhobar, lambda), c1 = rhobar/rhobar1,
+ * s1 = lambda/rhobar1, psi = s1 phibar, phibar = c1 phibar, and rhobar1 takes
+ * rhobar's place; sqrt(phibar^2 + sum psi^2) then estimates the norm of the
+ * stacked residual [b - A x; -lambda (x - x0)] (|phibar| when lambda = 0).
+ */
+int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
+                   const double *b, double *x, int K, double err, int x0_is_zero, double damp,
+                   double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
     og_t g = og_make(dims, par, angles);
     int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -564,7 +712,7 @@ int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
     double *tmpn = (double *)calloc((size_t)n, sizeof(double));
     int stop = OG_STOP_MAXITER, i = 0;
     double NB0 = sqrt(og_dot(b, b, m));
-    double phibar = NB0;
+    double phibar = NB0, res2 = 0.0;
     if (K <= 0) goto done;
     if (x0_is_zero) memset(x, 0, sizeof(double) * (size_t)n);
     if (x0_is_zero) memcpy(u, b, sizeof(double) * (size_t)m);
@@ -600,7 +748,14 @@ int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
                     for (int64_t t = 0; t < n; ++t) v[t] /= alpha_next;
             }
         }
-        /* Givens rotation */
+        /* damping rotation, then the Givens rotation */
+        if (damp != 0.0) {
+            double rhobar1 = sqrt(rhobar * rhobar + damp * damp);
+            double psi = (damp / rhobar1) * phibar;
+            res2 += psi * psi;
+            phibar = (rhobar / rhobar1) * phibar;
+            rhobar = rhobar1;
+        }
         double rho = sqrt(rhobar * rhobar + beta * beta);
         double c = rhobar / rho, s = beta / rho;
         double theta = s * alpha_next;
@@ -611,18 +766,26 @@ int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
         for (int64_t t = 0; t < n; ++t) w[t] = v[t] - (theta / rho) * w[t];
         alpha = alpha_next;
         i = i + 1;
-        if (history) history[i - 1] = NB0 > 0 ? fabs(phibar) / NB0 : 0.0;
+        double nb = sqrt(phibar * phibar + res2);
+        if (history) history[i - 1] = NB0 > 0 ? nb / NB0 : 0.0;
         if (!isfinite(phibar)) { stop = OG_STOP_NUMERIC; goto done; }
         if (beta == 0.0 || (!last && alpha_next == 0.0)) { stop = OG_STOP_BREAKDOWN; goto done; }
-        if (!(fabs(phibar) > err * NB0)) { stop = OG_STOP_TOL; goto done; }
+        if (!(nb > err * NB0)) { stop = OG_STOP_TOL; goto done; }
     }
     stop = OG_STOP_MAXITER;
 done:
-    if (out_nb) *out_nb = fabs(phibar);
+    if (out_nb) *out_nb = sqrt(phibar * phibar + res2);
     if (out_nb0) *out_nb0 = NB0;
     if (out_iters) *out_iters = i;
     free(u); free(tmpm); free(v); free(w); free(tmpn);
     return stop;
+}
+
+int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
+                const double *b, double *x, int K, double err, int x0_is_zero,
+                double *history, double *out_nb, double *out_nb0, int *out_iters)
+{
+    return oracle_lsqr_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0.0, history, out_nb, out_nb0, out_iters);
 }
 
 int oracle_num_threads(void)

@@ -13,8 +13,10 @@ passes device pointers and the current HIP stream.
 
 Volumes are torch tensors of shape (nz, ny, nx), projections (n_views, nv, nu),
 on the GPU, contiguous, with dtype float32, bfloat16 or float16 (storage type;
-accumulation is single precision and solver scalars double precision).  The
-solvers return the iterate x in float32 whatever the storage type of b.
+accumulation is single precision and solver scalars double precision), or
+float64 for the projector pair alone (double accumulation of the same
+single-precision weights).  The solvers return the iterate x in float32
+whatever the storage type of b.
 """
 from __future__ import annotations
 
@@ -26,7 +28,7 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import KctError, STOP_BREAKDOWN, STOP_MAXITER, STOP_NUMERIC, STOP_TOL
 
-__all__ = ["Geometry", "project", "backproject", "cgls", "lsqr", "SolveInfo", "KctError",
+__all__ = ["Geometry", "Batch", "project", "backproject", "diag_normal", "cgls", "lsqr", "SolveInfo", "KctError",
            "STOP_MAXITER", "STOP_TOL", "STOP_BREAKDOWN", "STOP_NUMERIC"]
 
 
@@ -43,7 +45,9 @@ def _dtype_code(t):
         return _lib.KCT_BF16
     if t == torch.float16:
         return _lib.KCT_F16
-    raise TypeError(f"unsupported storage dtype {t} (float32, bfloat16 or float16)")
+    if t == torch.float64:
+        return _lib.KCT_F64
+    raise TypeError(f"unsupported storage dtype {t} (float32, bfloat16, float16 or float64)")
 
 
 def _stream_handle(device):
@@ -124,9 +128,11 @@ class Geometry:
         _lib.check(_lib.load().kct_project_workspace_size(self.handle, _dtype_code(dtype), ctypes.byref(n)))
         return n.value
 
-    def solver_workspace_bytes(self, dtype, solver):
+    def solver_workspace_bytes(self, dtype, solver, jacobi: bool = False):
         n = ctypes.c_size_t()
         code = {"cgls": _lib.KCT_SOLVER_CGLS, "lsqr": _lib.KCT_SOLVER_LSQR}[solver]
+        if jacobi:
+            code |= _lib.KCT_SOLVER_WITH_JACOBI
         _lib.check(_lib.load().kct_solver_workspace_size(self.handle, _dtype_code(dtype), code, ctypes.byref(n)))
         return n.value
 
@@ -211,7 +217,21 @@ class SolveInfo:
     history: Optional[object] = None
 
 
-def _solve(which, g, b, K, x0, err, history, workspace, out):
+def diag_normal(g: Geometry, out=None):
+    """diag(A^T A) = sum_i w_ij^2 per voxel (float32 volume), the diagonal that
+    Jacobi preconditioning inverts."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty(g.vol_shape, dtype=torch.float32, device=g.device)
+    _check_tensor(out, g.vol_shape, "out", g.device)
+    if out.dtype != torch.float32:
+        raise TypeError("out must be float32")
+    with torch.cuda.device(g.device):
+        _lib.check(_lib.load().kct_diag_normal(g.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle(g.device)))
+    return out
+
+
+def _solve(which, g, b, K, x0, err, history, workspace, out, tikhonov=0.0, jacobi=False, recompute_every=0):
     """b (and the workspace vectors) in b's storage dtype; the iterate x is float32."""
     torch = _torch()
     _check_tensor(b, g.proj_shape, "b", g.device)
@@ -226,9 +246,9 @@ def _solve(which, g, b, K, x0, err, history, workspace, out):
             out.copy_(x0)
     hist = torch.zeros(max(int(K), 1), dtype=torch.float64, device=g.device) if history else None
     opts = _lib.SolveOpts(int(K), float(err), int(x0 is None), ctypes.c_void_p(hist.data_ptr()) if hist is not None
-                          else None)
+                          else None, float(tikhonov), int(bool(jacobi)), int(recompute_every))
     if workspace is None:
-        workspace = _workspace(g.solver_workspace_bytes(b.dtype, which), g.device)
+        workspace = _workspace(g.solver_workspace_bytes(b.dtype, which, jacobi=bool(jacobi)), g.device)
     ws_bytes = workspace.numel() * workspace.element_size()
     info = _lib.SolveInfo()
     fn = _lib.load().kct_cgls_solve if which == "cgls" else _lib.load().kct_lsqr_solve
@@ -245,11 +265,112 @@ def _solve(which, g, b, K, x0, err, history, workspace, out):
     return out, res
 
 
-def cgls(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None):
-    """CGLS with delayed residual computation (Algorithm 1): returns (x_K, SolveInfo)."""
-    return _solve("cgls", g, b, K, x0, err, history, workspace, out)
+def cgls(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None,
+         tikhonov: float = 0.0, jacobi: bool = False, recompute_every: int = 0):
+    """CGLS with delayed residual computation (Algorithm 1): returns (x_K, SolveInfo).
+
+    tikhonov = lambda adds lambda^2 |x|^2 to the objective; jacobi preconditions
+    with diag(A^T A)^(-1/2); recompute_every = k recomputes e = b - A x after
+    every k-th iteration (see kct_solve_opts in include/kct.h)."""
+    return _solve("cgls", g, b, K, x0, err, history, workspace, out, tikhonov, jacobi, recompute_every)
 
 
-def lsqr(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None):
-    """LSQR (Paige & Saunders), iterations aligned with CGLS: returns (x_K, SolveInfo)."""
-    return _solve("lsqr", g, b, K, x0, err, history, workspace, out)
+def lsqr(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = False, workspace=None, out=None,
+         tikhonov: float = 0.0):
+    """LSQR (Paige & Saunders), iterations aligned with CGLS: returns (x_K, SolveInfo).
+
+    tikhonov = lambda > 0 (damping, x0 = 0 only) minimises |b - A x|^2 + lambda^2 |x|^2;
+    info.nb is then the norm of the stacked residual [b - A x; -lambda x]."""
+    return _solve("lsqr", g, b, K, x0, err, history, workspace, out, tikhonov)
+
+
+class Batch:
+    """Batched CGLS over independent reconstructions with their own geometries
+    (kct_batch_* in include/kct.h): every step of Algorithm 1 is one launch for
+    all instances, one iteration is replayed as a HIP graph.  FP32 storage.
+
+        batch = Batch([g1, g2, ...])
+        batch.tune(cache="tune.txt")            # optional: forward variant per instance
+        xs, infos = batch.cgls([b1, b2, ...], K)
+    """
+
+    def __init__(self, geometries: Sequence[Geometry]):
+        torch = _torch()
+        if not geometries:
+            raise ValueError("a batch needs at least one geometry")
+        self.geometries = list(geometries)
+        self.device = self.geometries[0].device
+        for g in self.geometries:
+            if g.device != self.device:
+                raise ValueError("all geometries of a batch must be on one device")
+        arr = (ctypes.c_void_p * len(self.geometries))(*[g.handle.value for g in self.geometries])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_batch_create(arr, len(self.geometries), ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("batch was closed")
+        return self._h
+
+    def workspace_bytes(self):
+        n = ctypes.c_size_t()
+        _lib.check(_lib.load().kct_batch_workspace_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def _workspace(self, workspace):
+        if workspace is not None:
+            return workspace
+        if self._ws is None:
+            self._ws = _workspace(self.workspace_bytes(), self.device)
+        return self._ws
+
+    def tune(self, cache: Optional[str] = None, workspace=None):
+        """Choose each instance's forward variant by timing (see kct_batch_tune)."""
+        torch = _torch()
+        ws = self._workspace(workspace)
+        with torch.cuda.device(self.device):
+            _lib.check(_lib.load().kct_batch_tune(self.handle, ctypes.c_void_p(ws.data_ptr()),
+                                                  ws.numel() * ws.element_size(),
+                                                  cache.encode() if cache else None, _stream_handle(self.device)))
+
+    def cgls(self, bs, K: int, err: float = 0.0, graph: bool = True, workspace=None, outs=None):
+        """x_i = CGLS_K(b_i) from x0 = 0 for every instance: returns (list of x, list of SolveInfo)."""
+        torch = _torch()
+        n = len(self.geometries)
+        if len(bs) != n:
+            raise ValueError(f"expected {n} projection tensors")
+        if outs is None:
+            outs = [torch.empty(g.vol_shape, dtype=torch.float32, device=self.device) for g in self.geometries]
+        for g, b, x in zip(self.geometries, bs, outs):
+            _check_tensor(b, g.proj_shape, "b", self.device)
+            _check_tensor(x, g.vol_shape, "x", self.device)
+            if b.dtype != torch.float32 or x.dtype != torch.float32:
+                raise TypeError("batched CGLS uses float32 storage")
+        ws = self._workspace(workspace)
+        bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in bs])
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in outs])
+        opts = _lib.SolveOpts(int(K), float(err), 1, None, 0.0, 0, 0)
+        infos = (_lib.SolveInfo * n)()
+        with torch.cuda.device(self.device):
+            st = _lib.load().kct_batch_cgls_solve(self.handle, bp, xp, ctypes.byref(opts), int(bool(graph)),
+                                                   ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                                   infos, _stream_handle(self.device))
+        if st != _lib.KCT_OK:
+            _lib.check(st)
+        res = [SolveInfo(i.iterations, i.nb0, i.nb, i.nr2, i.stop_reason) for i in infos]
+        return outs, res
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _lib.load().kct_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

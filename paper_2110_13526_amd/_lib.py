@@ -13,15 +13,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkct.so")
 
 KCT_OK, KCT_ERR_INVALID_ARG, KCT_ERR_UNSUPPORTED, KCT_ERR_HIP, KCT_ERR_WORKSPACE, KCT_ERR_NUMERIC = range(6)
-KCT_F32, KCT_BF16, KCT_F16 = 0, 1, 2
-KCT_SOLVER_CGLS, KCT_SOLVER_LSQR = 0, 1
+KCT_F32, KCT_BF16, KCT_F16, KCT_F64 = 0, 1, 2, 3
+KCT_SOLVER_CGLS, KCT_SOLVER_LSQR, KCT_SOLVER_WITH_JACOBI = 0, 1, 0x100
 STOP_MAXITER, STOP_TOL, STOP_BREAKDOWN, STOP_NUMERIC = 0, 1, 2, 3
 
 # Every symbol include/kct.h declares.
 EXPORTS = (
     "kct_geometry_create", "kct_geometry_destroy", "kct_geometry_dims", "kct_project_workspace_size",
     "kct_project", "kct_backproject", "kct_solver_workspace_size", "kct_cgls_solve", "kct_lsqr_solve",
-    "kct_last_error",
+    "kct_diag_normal", "kct_batch_create", "kct_batch_destroy", "kct_batch_workspace_size", "kct_batch_tune",
+    "kct_batch_cgls_solve", "kct_last_error",
 )
 
 
@@ -42,7 +43,8 @@ class ConeDesc(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("err_tol", ctypes.c_double), ("x0_is_zero", ctypes.c_int32),
-                ("history", ctypes.c_void_p)]
+                ("history", ctypes.c_void_p), ("tikhonov", ctypes.c_double), ("jacobi", ctypes.c_int32),
+                ("recompute_every", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -88,6 +90,19 @@ def load():
         f.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.POINTER(SolveOpts), vp, ctypes.c_size_t,
                       ctypes.POINTER(SolveInfo), vp]
         f.restype = st
+    L.kct_diag_normal.argtypes = [vp, vp, vp]
+    L.kct_diag_normal.restype = st
+    L.kct_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
+    L.kct_batch_create.restype = st
+    L.kct_batch_destroy.argtypes = [vp]
+    L.kct_batch_destroy.restype = None
+    L.kct_batch_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.kct_batch_workspace_size.restype = st
+    L.kct_batch_tune.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_char_p, vp]
+    L.kct_batch_tune.restype = st
+    L.kct_batch_cgls_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                                       ctypes.c_int32, vp, ctypes.c_size_t, ctypes.POINTER(SolveInfo), vp]
+    L.kct_batch_cgls_solve.restype = st
     L.kct_last_error.argtypes = []
     L.kct_last_error.restype = ctypes.c_char_p
     _lib = L

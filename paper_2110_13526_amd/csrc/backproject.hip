@@ -8,6 +8,9 @@
 // round-robin in dispatch order) owns a contiguous range of bricks: bricks that
 // neighbour each other share most of their detector shadow, so the staged
 // projection values are reused from the XCD's own L2.
+#include <type_traits>
+
+#include "kct_batch.h"
 #include "kct_gather.h"
 #include "kct_internal.h"
 #include "kct_weights.h"
@@ -27,20 +30,22 @@ __device__ __forceinline__ double bwd_block_sum(double v)
     return r;
 }
 
+// backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
+// backprojection into one volume; its partial sum goes to partials[w].
 template <typename T, int EPI>
-__global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
-                                                  T *__restrict__ out_z, const Scalars *__restrict__ sc,
-                                                  double *__restrict__ partials, const int *__restrict__ skip, int nbx,
-                                                  int nby, int nbz)
+__device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *__restrict__ proj,
+                                               T *__restrict__ out, T *__restrict__ out_z,
+                                               const Scalars *__restrict__ sc, double *__restrict__ partials,
+                                               int nbx, int nby, int nbz, const float *__restrict__ aux)
 {
-    if (skip && *skip) return;
-    __shared__ PixStage s_pix[CH_ROWS * CH_COLS];
+    using A = acc_t<T>;
+    constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
+    __shared__ PixStage<A> s_pix[CH_ROWS * CH_COLS];
     __shared__ ColStage s_col[CH_COLS];
     __shared__ int s_fp[4];
 
     // XCD-aware brick assignment
     const int nb = nbx * nby * nbz;
-    const int w = blockIdx.x;
     const int b = (nb % NXCD == 0) ? (w % NXCD) * (nb / NXCD) + w / NXCD : w;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int ix = bx * BX + (int)(threadIdx.x % BX);
@@ -61,9 +66,9 @@ __global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restri
     const int pcell = parallel_cell(-g.zc, g.hz);
     const float pzadd = ((float)pcell - g.hz + 0.5f) + g.zc;
 
-    float acc[TZ];
+    A acc[TZ];
 #pragma unroll
-    for (int j = 0; j < TZ; ++j) acc[j] = 0.0f;
+    for (int j = 0; j < TZ; ++j) acc[j] = 0;
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
@@ -91,7 +96,7 @@ __global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restri
         __syncthreads();
         const int u0 = s_fp[0], u1 = s_fp[1], v0 = s_fp[2], v1 = s_fp[3];
         __syncthreads();
-        const T *pk = proj + (size_t)k * g.nv * g.nu;
+        const T *pk = SQ ? proj : proj + (size_t)k * g.nv * g.nu;  // not read when SQ
         const ColParam *ck = g.cols + (size_t)k * g.nu;
         for (int cu0 = u0; cu0 <= u1; cu0 += CH_COLS) {
             const int ncol = u1 - cu0 + 1 < CH_COLS ? u1 - cu0 + 1 : CH_COLS;
@@ -104,11 +109,11 @@ __global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restri
                     const ColParam cp = ck[cu0 + c];
                     const RowParam rp = g.rows[cv0 + r];
                     const bool par = rp.inv_qz == 0.0f;
-                    PixStage ps;
+                    PixStage<A> ps;
                     ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
                     ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
-                    ps.le = ray_length_per_xi(cp.lxy2, rp.qz, cp.gp) * to_f32(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
-                    ps.pad = 0.0f;
+                    const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
+                    ps.le = SQ ? L * L : L * to_acc(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
                     s_pix[r * CH_COLS + c] = ps;
                 }
                 if (threadIdx.x < ncol) {
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restri
                 }
                 __syncthreads();
                 // 3. gather
-                if (valid) gather_chunk(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
+                if (valid) gather_chunk<A, SQ>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
                 __syncthreads();
             }
         }
@@ -135,22 +140,44 @@ __global__ __launch_bounds__(256, 4) void k_backward(GeoDev g, const T *__restri
             if (j >= nzb) continue;
             const int iz = iz0 + j;
             const size_t vox = ((size_t)iz * g.ny + iy) * g.nx + ix;
-            float o;
-            if (EPI == BWD_LSQR0) o = (float)sc->bwd_c1 * acc[j];
-            else if (EPI == BWD_LSQR) o = (float)sc->bwd_c1 * acc[j] - (float)sc->bwd_c2 * to_f32(out[vox]);
-            else if (EPI == BWD_NORM) o = sc->bwd_scale * acc[j];
+            A o;
+            if (EPI == BWD_LSQR0) o = (A)sc->bwd_c1 * acc[j];
+            else if (EPI == BWD_LSQR) o = (A)sc->bwd_c1 * acc[j] - (A)sc->bwd_c2 * to_acc(out[vox]);
+            else if (EPI == BWD_NORM) o = (A)sc->bwd_scale * acc[j];
+            else if (EPI == BWD_TIK) o = (A)sc->bwd_scale * acc[j] - (A)sc->tik_r * (A)aux[vox];
+            else if (EPI == BWD_JACOBI) o = (A)aux[vox] * acc[j];
+            else if (EPI == BWD_DIAG_INV) o = acc[j] > 0 ? (A)1 / acc[j] : (A)0;
             else o = acc[j];
-            const T st = from_f32<T>(o);
+            const T st = store_as<T>(o);
             out[vox] = st;
             if (EPI == BWD_LSQR0 || EPI == BWD_LSQR) out_z[((size_t)iy * g.nx + ix) * g.nz + iz] = st;
-            const double od = (double)to_f32(st);
-            sq += od * od;
+            if (EPI == BWD_JACOBI) {  // |M A^T e|^2 with M^2 = aux: the preconditioned residual norm
+                const double a = (double)acc[j];
+                sq += (double)aux[vox] * a * a;
+            } else {
+                const double od = (double)to_acc(st);
+                sq += od * od;
+            }
         }
     }
-    if (EPI != BWD_PLAIN) {
+    if (EPI != BWD_PLAIN && EPI != BWD_DIAG && EPI != BWD_DIAG_INV) {
         const double bs = bwd_block_sum(sq);
-        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+        if (threadIdx.x == 0) partials[w] = bs;
     }
+}
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 4 : 2) void k_backward(GeoDev g, const T *__restrict__ proj,
+                                                                                T *__restrict__ out,
+                                                                                T *__restrict__ out_z,
+                                                                                const Scalars *__restrict__ sc,
+                                                                                double *__restrict__ partials,
+                                                                                const int *__restrict__ skip, int nbx,
+                                                                                int nby, int nbz,
+                                                                                const float *__restrict__ aux)
+{
+    if (skip && *skip) return;
+    backward_block<T, EPI>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux);
 }
 
 static void bwd_grid(const GeoDev &g, int &nbx, int &nby, int &nbz)
@@ -160,6 +187,32 @@ static void bwd_grid(const GeoDev &g, int &nbx, int &nby, int &nbz)
     nbz = (g.nz + TZ - 1) / TZ;
 }
 
+int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz)
+{
+    bwd_grid(g, nbx, nby, nbz);
+    return (int64_t)nbx * nby * nbz;
+}
+
+// Batched r = A^T e with |r|^2 partials for every instance.
+__global__ __launch_bounds__(256, 4) void kb_backward(const BatchInst *__restrict__ B,
+                                                      const int64_t *__restrict__ off, int count)
+{
+    const int64_t w = blockIdx.x;
+    const int i = batch_find(off, count, w);
+    const BatchInst *bi = B + i;
+    if (bi->sc->done) return;
+    const int64_t lw = w - off[i];
+    if (lw >= (int64_t)bi->nbx * bi->nby * bi->nbz) return;  // padding of the instance's grid
+    backward_block<float, BWD_NORM>(bi->g, (int)lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx, bi->nby,
+                                    bi->nbz, nullptr);
+}
+
+hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(kb_backward, dim3((unsigned)blocks), dim3(256), 0, st, B, off, count);
+    return hipGetLastError();
+}
+
 int64_t backward_num_blocks(const GeoDev &g)
 {
     int nbx, nby, nbz;
@@ -167,42 +220,55 @@ int64_t backward_num_blocks(const GeoDev &g)
     return (int64_t)nbx * nby * nbz;
 }
 
+template <typename T, int EPI>
+static void launch_bwd(const GeoDev &g, const T *proj, T *out, T *out_z, const Scalars *sc, double *partials,
+                       const int *skip, dim3 grid, int nbx, int nby, int nbz, const float *aux, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_backward<T, EPI>), grid, dim3(256), 0, st, g, proj, out, out_z, sc, partials, skip, nbx, nby,
+                       nbz, aux);
+}
+
 template <typename T>
 hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
-                           double *partials, const int *skip, hipStream_t st)
+                           double *partials, const int *skip, hipStream_t st, const float *aux)
 {
     int nbx, nby, nbz;
     bwd_grid(g, nbx, nby, nbz);
-    dim3 grid((unsigned)(nbx * nby * nbz));
-    dim3 block(256);
-    switch (epi) {
-    case BWD_PLAIN:
-        hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
-                           nbx, nby, nbz);
-        break;
-    case BWD_NORM:
-        hipLaunchKernelGGL((k_backward<T, BWD_NORM>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
-                           nbx, nby, nbz);
-        break;
-    case BWD_LSQR0:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR0>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
-                           nbx, nby, nbz);
-        break;
-    case BWD_LSQR:
-        hipLaunchKernelGGL((k_backward<T, BWD_LSQR>), grid, block, 0, st, g, proj, out, out_z, sc, partials, skip,
-                           nbx, nby, nbz);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(nbx * nby * nbz));
+    if constexpr (std::is_same<T, double>::value) {  // double storage: plain backprojection only
+        if (epi != BWD_PLAIN) return hipErrorInvalidValue;
+        launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+    } else {
+        switch (epi) {
+        case BWD_PLAIN: launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_NORM: launch_bwd<T, BWD_NORM>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_LSQR0: launch_bwd<T, BWD_LSQR0>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_LSQR: launch_bwd<T, BWD_LSQR>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_TIK: launch_bwd<T, BWD_TIK>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_JACOBI: launch_bwd<T, BWD_JACOBI>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        default:
+            if constexpr (std::is_same<T, float>::value) {  // the diagonal of A^T A is single precision
+                if (epi == BWD_DIAG) {
+                    launch_bwd<T, BWD_DIAG>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+                    break;
+                }
+                if (epi == BWD_DIAG_INV) {
+                    launch_bwd<T, BWD_DIAG_INV>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+                    break;
+                }
+            }
+            return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
 
 #define KCT_BINST(T)                                                                                             \
     template hipError_t launch_backward<T>(const GeoDev &, const T *, T *, T *, int, const Scalars *, double *, \
-                                           const int *, hipStream_t);
+                                           const int *, hipStream_t, const float *);
 KCT_BINST(float)
 KCT_BINST(bf16)
 KCT_BINST(_Float16)
+KCT_BINST(double)
 
 }  // namespace kct

@@ -24,6 +24,7 @@ size_t elem_size(kct_dtype t)
     case KCT_F32: return 4;
     case KCT_BF16: return 2;
     case KCT_F16: return 2;
+    case KCT_F64: return 8;
     default: return 0;
     }
 }
@@ -41,23 +42,28 @@ int64_t num_partials(const Geometry *g)
 }
 
 struct SolverLayout {
-    size_t scal, part, v0, v1, v2, p0, p1, total;
+    size_t scal, part, part2, v0, v1, v2, p0, p1, m2, total;
 };
 
-// [Scalars][partials][3 volumes][2 (CGLS) or 1 (LSQR) projections]
+// [Scalars][partials][partials of |d|^2][3 volumes][2 (CGLS) or 1 (LSQR)
+// projections][CGLS with Jacobi: one float volume, the preconditioner]
 SolverLayout solver_layout(const Geometry *g, kct_dtype t, int solver)
 {
     SolverLayout L{};
+    const bool jacobi = (solver & KCT_SOLVER_WITH_JACOBI) != 0;
+    solver &= ~KCT_SOLVER_WITH_JACOBI;
     size_t es = elem_size(t);
     size_t V = align256((size_t)nvox(g) * es), P = align256((size_t)nrays(g) * es);
     L.scal = 0;
     L.part = align256(sizeof(Scalars));
-    L.v0 = L.part + align256((size_t)num_partials(g) * sizeof(double));
+    L.part2 = L.part + align256((size_t)num_partials(g) * sizeof(double));
+    L.v0 = L.part2 + align256((size_t)cgls_d_num_blocks(g->dev) * sizeof(double));
     L.v1 = L.v0 + V;
     L.v2 = L.v1 + V;
     L.p0 = L.v2 + V;
     L.p1 = L.p0 + P;
-    L.total = (solver == KCT_SOLVER_CGLS) ? L.p1 + P : L.p1;
+    L.m2 = (solver == KCT_SOLVER_CGLS) ? L.p1 + P : L.p1;
+    L.total = jacobi ? L.m2 + align256((size_t)nvox(g) * sizeof(float)) : L.m2;
     return L;
 }
 
@@ -89,6 +95,19 @@ kct_status check_dtype(kct_dtype t, const char *fn)
     return KCT_OK;
 }
 
+// The solvers run on the 32- and 16-bit storage types; double storage is
+// offered for the projector pair only.
+kct_status check_solver_dtype(kct_dtype t, const char *fn)
+{
+    kct_status s = check_dtype(t, fn);
+    if (s != KCT_OK) return s;
+    if (t == KCT_F64) {
+        set_error(std::string(fn) + ": the solvers do not support double storage (use F32, BF16 or F16)");
+        return KCT_ERR_UNSUPPORTED;
+    }
+    return KCT_OK;
+}
+
 bool misaligned(const void *p) { return ((uintptr_t)p & 15u) != 0; }
 
 template <typename T> kct_dtype dtype_of();
@@ -109,7 +128,10 @@ struct StorageScales {
     double sr, sp, sw;
 };
 
-__global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *history, StorageScales ss)
+// Scalars at the start of a solve.  lambda: CGLS Tikhonov parameter (tik,
+// applied through r and NP2) or LSQR damping (damp).
+__global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *history, StorageScales ss,
+                               double tik, double damp)
 {
     if (threadIdx.x != 0) return;
     Scalars s;
@@ -122,6 +144,9 @@ __global__ void k_init_scalars(Scalars *sc, int maxiter, double err, double *his
     s.sw = ss.sw;
     s.fwd_scale = (float)(ss.sr / ss.sp);
     s.bwd_scale = (float)(1.0 / ss.sr);
+    s.tik_r = (float)(tik * tik / ss.sr);   // r_stored = A^T e / sr - (lambda^2 / sr) x
+    s.tik_d2 = tik * tik * ss.sr * ss.sr;   // lambda^2 |d|^2 with d = sr * d_stored
+    s.damp = damp;
     *sc = s;
 }
 
@@ -204,29 +229,45 @@ kct_status read_info(Scalars *sc, kct_solve_info *info, hipStream_t st, const ch
     return KCT_OK;
 }
 
-// CGLS with delayed residual computation (Algorithm 1).
+// CGLS with delayed residual computation (Algorithm 1), with the options of
+// kct_solve_opts: Tikhonov term (CGLS on [A; lambda I]: r = A^T e - lambda^2 x,
+// NP2 = |A d|^2 + lambda^2 |d|^2), Jacobi right preconditioning (r = M^2 A^T e
+// is stored, so d and x stay in the unpreconditioned space and NR2 = |M A^T e|^2
+// comes from the epilogue's partials), periodic recomputation of e.
 template <typename T>
 kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_opts *o, void *ws,
                   kct_solve_info *info, hipStream_t st)
 {
     const char *fn = "kct_cgls_solve";
-    const SolverLayout L = solver_layout(g, dtype_of<T>(), KCT_SOLVER_CGLS);
+    const bool jacobi = o->jacobi != 0;
+    const double lambda = o->tikhonov;
+    const int re = o->recompute_every;
+    const SolverLayout L =
+        solver_layout(g, dtype_of<T>(), KCT_SOLVER_CGLS | (jacobi ? KCT_SOLVER_WITH_JACOBI : 0));
     char *w = (char *)ws;
     Scalars *sc = (Scalars *)(w + L.scal);
     double *part = (double *)(w + L.part);
+    double *dpart = lambda > 0.0 ? (double *)(w + L.part2) : nullptr;
     T *d = (T *)(w + L.v0), *dz = (T *)(w + L.v1), *r = (T *)(w + L.v2);
     T *e = (T *)(w + L.p0), *p = (T *)(w + L.p1);
+    float *m2 = jacobi ? (float *)(w + L.m2) : nullptr;
     const T *b = (const T *)bv;
     float *x = (float *)xv;
     const GeoDev &G = g->dev;
     const int64_t n = nvox(g), m = nrays(g);
     const int64_t nf = forward_num_blocks(G), nbk = backward_num_blocks(G), ns = stream_num_blocks();
+    const int64_t nd = lambda > 0.0 ? cgls_d_num_blocks(G) : 0;
     const int K = o->max_iter;
     const int *done = &sc->done;
+    // r = A^T e in the variant's form; aux is x (Tikhonov) or M^2 (Jacobi)
+    const int repi = jacobi ? BWD_JACOBI : (lambda > 0.0 ? BWD_TIK : BWD_NORM);
+    const float *raux = jacobi ? m2 : (lambda > 0.0 ? x : nullptr);
 
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history,
-                       storage_scales(g, dtype_of<T>()));
+                       storage_scales(g, dtype_of<T>()), lambda, 0.0);
     KCT_TRY(hipGetLastError());
+    if (jacobi)  // M^2 = 1 / diag(A^T A), 0 where the diagonal is 0
+        KCT_TRY(launch_backward<float>(G, nullptr, m2, nullptr, BWD_DIAG_INV, nullptr, nullptr, nullptr, st));
     // NB0 = |b|
     KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
     KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
@@ -241,30 +282,37 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         KCT_TRY((launch_forward<float, T>(G, x, xz0, e, b, FWD_BMINUS, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_NB_INIT, st));
     }
+    // x += alpha d; e -= alpha p (or e = b - A x every re-th iteration); NB; i = i + 1
+    auto step_end = [&](int i) -> kct_status {
+        KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
+        if (re > 0 && i % re == 0) {
+            KCT_TRY((launch_forward<float, T>(G, x, nullptr, e, b, FWD_BMINUS, sc, part, done, st)));
+            KCT_TRY(launch_finalize(sc, part, nf, F_NB, st));
+        } else {
+            KCT_TRY(launch_cgls_e<T>(e, p, sc, m, part, st));
+            KCT_TRY(launch_finalize(sc, part, ns, F_NB, st));
+        }
+        return KCT_OK;
+    };
     // r = A^T e; d = r; NR2_old = |r|^2
-    KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
+    KCT_TRY(launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux));
     KCT_TRY(launch_finalize(sc, part, nbk, F_NR2_INIT, st));
-    KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 1, st));
-    // p = A d; NP2 = |p|^2; alpha = NR2_old / NP2
+    KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 1, st, dpart));
+    // p = A d; NP2 = |p|^2 (+ lambda^2 |d|^2); alpha = NR2_old / NP2
     KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
-    KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
-    // x = x + alpha d; e = e - alpha p; NB = |e|; i = 1
-    KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
-    KCT_TRY(launch_cgls_e<T>(e, p, sc, m, part, st));
-    KCT_TRY(launch_finalize(sc, part, ns, F_NB, st));
+    KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st, dpart, nd));
+    kct_status s = step_end(1);
+    if (s != KCT_OK) return s;
     for (int it = 1; it < K; ++it) {
         // r = A^T e; NR2_now = |r|^2; beta = NR2_now / NR2_old; NR2_old = NR2_now
-        KCT_TRY(launch_backward<T>(G, e, r, nullptr, BWD_NORM, sc, part, done, st));
+        KCT_TRY(launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux));
         KCT_TRY(launch_finalize(sc, part, nbk, F_BETA, st));
         // d = r + beta d
-        KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 0, st));
+        KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 0, st, dpart));
         // p = A d; NP2; alpha
         KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
-        KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st));
-        // x += alpha d; e -= alpha p; NB; i = i + 1 (and the while test)
-        KCT_TRY(launch_cgls_x<T>(x, d, sc, n, st));
-        KCT_TRY(launch_cgls_e<T>(e, p, sc, m, part, st));
-        KCT_TRY(launch_finalize(sc, part, ns, F_NB, st));
+        KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st, dpart, nd));
+        if ((s = step_end(it + 1)) != KCT_OK) return s;
     }
     return read_info<T>(sc, info, st, fn, KCT_SOLVER_CGLS);
 }
@@ -291,7 +339,7 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
     const int *done = &sc->done;
 
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(64), 0, st, sc, K, o->err_tol, o->history,
-                       storage_scales(g, dtype_of<T>()));
+                       storage_scales(g, dtype_of<T>()), 0.0, o->tikhonov);
     KCT_TRY(hipGetLastError());
     KCT_TRY(launch_norm2<T>(b, m, part, nullptr, st));
     KCT_TRY(launch_finalize(sc, part, ns, F_NB0, st));
@@ -331,7 +379,7 @@ kct_status check_solve_args(kct_geometry h, kct_dtype t, const void *b, void *x,
 {
     kct_status s = check_geometry(h, fn);
     if (s != KCT_OK) return s;
-    if ((s = check_dtype(t, fn)) != KCT_OK) return s;
+    if ((s = check_solver_dtype(t, fn)) != KCT_OK) return s;
     if (!b || !x || !o) {
         set_error(std::string(fn) + ": b, x and opts must not be NULL");
         return KCT_ERR_INVALID_ARG;
@@ -344,7 +392,24 @@ kct_status check_solve_args(kct_geometry h, kct_dtype t, const void *b, void *x,
         set_error(std::string(fn) + ": max_iter must be >= 0 and err_tol finite and >= 0");
         return KCT_ERR_INVALID_ARG;
     }
+    if (!(o->tikhonov >= 0.0) || !std::isfinite(o->tikhonov) || o->recompute_every < 0) {
+        set_error(std::string(fn) + ": tikhonov must be finite and >= 0, recompute_every >= 0");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (solver == KCT_SOLVER_LSQR && (o->jacobi || o->recompute_every)) {
+        set_error(std::string(fn) + ": jacobi and recompute_every are CGLS options");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (solver == KCT_SOLVER_LSQR && o->tikhonov > 0.0 && !o->x0_is_zero) {
+        set_error(std::string(fn) + ": LSQR with tikhonov > 0 needs x0 = 0 (its damping penalises x - x0)");
+        return KCT_ERR_UNSUPPORTED;
+    }
+    if (o->jacobi && (o->tikhonov > 0.0 || t == KCT_F16)) {
+        set_error(std::string(fn) + ": jacobi is not available with tikhonov > 0 or F16 storage");
+        return KCT_ERR_UNSUPPORTED;
+    }
     const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    if (o->jacobi) solver |= KCT_SOLVER_WITH_JACOBI;
     size_t need = solver_layout(g, t, solver).total;
     if (!ws || ws_bytes < need) {
         set_error(std::string(fn) + ": workspace of " + std::to_string(ws_bytes) + " bytes, need " +
@@ -437,7 +502,8 @@ kct_status kct_project(kct_geometry h, kct_dtype t, const void *x, void *b, void
     switch (t) {
     case KCT_F32: return project_t<float>(g, x, b, ws, stream);
     case KCT_BF16: return project_t<bf16>(g, x, b, ws, stream);
-    default: return project_t<_Float16>(g, x, b, ws, stream);
+    case KCT_F16: return project_t<_Float16>(g, x, b, ws, stream);
+    default: return project_t<double>(g, x, b, ws, stream);
     }
 }
 
@@ -459,7 +525,8 @@ kct_status kct_backproject(kct_geometry h, kct_dtype t, const void *b, void *x, 
     switch (t) {
     case KCT_F32: return backproject_t<float>(g, b, x, stream);
     case KCT_BF16: return backproject_t<bf16>(g, b, x, stream);
-    default: return backproject_t<_Float16>(g, b, x, stream);
+    case KCT_F16: return backproject_t<_Float16>(g, b, x, stream);
+    default: return backproject_t<double>(g, b, x, stream);
     }
 }
 
@@ -469,9 +536,10 @@ kct_status kct_solver_workspace_size(kct_geometry h, kct_dtype t, int32_t solver
         set_error("kct_solver_workspace_size: NULL argument");
         return KCT_ERR_INVALID_ARG;
     }
-    kct_status s = check_dtype(t, "kct_solver_workspace_size");
+    kct_status s = check_solver_dtype(t, "kct_solver_workspace_size");
     if (s != KCT_OK) return s;
-    if (solver != KCT_SOLVER_CGLS && solver != KCT_SOLVER_LSQR) {
+    if (solver != KCT_SOLVER_CGLS && solver != KCT_SOLVER_LSQR &&
+        solver != (KCT_SOLVER_CGLS | KCT_SOLVER_WITH_JACOBI)) {
         set_error("kct_solver_workspace_size: unknown solver");
         return KCT_ERR_INVALID_ARG;
     }
@@ -503,6 +571,20 @@ kct_status kct_lsqr_solve(kct_geometry h, kct_dtype t, const void *b, void *x, c
     case KCT_BF16: return lsqr_t<bf16>(g, b, x, opts, ws, info, stream);
     default: return lsqr_t<_Float16>(g, b, x, opts, ws, info, stream);
     }
+}
+
+kct_status kct_diag_normal(kct_geometry h, float *out, hipStream_t stream)
+{
+    const char *fn = "kct_diag_normal";
+    kct_status s = check_geometry(h, fn);
+    if (s != KCT_OK) return s;
+    if (!out || misaligned(out)) {
+        set_error("kct_diag_normal: out must be a 16-byte aligned device pointer");
+        return KCT_ERR_INVALID_ARG;
+    }
+    const Geometry *g = reinterpret_cast<const Geometry *>(h);
+    KCT_TRY(launch_backward<float>(g->dev, nullptr, out, nullptr, BWD_DIAG, nullptr, nullptr, nullptr, stream));
+    return KCT_OK;
 }
 
 const char *kct_last_error(void) { return g_last_error.c_str(); }

@@ -40,10 +40,14 @@ struct ColStage {  // per staged detector column: in-plane ray parameters
 // and zc moved to the middle of the z-cell those rays lie in: the crossings of
 // every z-plane are then +-inf and the general formula gives exactly the
 // parallel-ray weights of kct_weights.h.
-struct PixStage {
+template <typename A> struct PixStage {
     float zc, czr;
-    float le;      // L * e
+    A le;          // L * e, in the accumulator precision
     float pad;
+};
+template <> struct PixStage<double> {  // the same 16 bytes with a double L * e
+    float zc, czr;
+    double le;
 };
 
 // Detector coordinates (column, row; fractional pixel indices) of the ray
@@ -95,9 +99,12 @@ __host__ __device__ __forceinline__ void column_interval(const ColStage &cs, flo
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
 // accumulators of its voxels (ix, iy, iz0 + j), j < nzb, for every staged ray
 // i = (column cu0 + c, row cv0 + r); s_pix[r * CH_COLS + c] describes ray i.
+// SQ: accumulate w_ij^2 * le instead of w_ij * le (with le = L^2 this sums the
+// squared weights, the diagonal of A^T A).
+template <typename A, bool SQ = false>
 __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const ViewParam &vp, int ix, int iy, int iz0,
-                                                      int nzb, const PixStage *s_pix, const ColStage *s_col, int cu0,
-                                                      int ncol, int cv0, int nrow, float (&acc)[TZ])
+                                                      int nzb, const PixStage<A> *s_pix, const ColStage *s_col,
+                                                      int cu0, int ncol, int cv0, int nrow, A (&acc)[TZ])
 {
     int ixi, ieta;
     float hxi, heta;
@@ -160,14 +167,14 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
                 const float mb = mbz0 + (float)j;
                 const float mb1 = mb + 1.0f;
                 for (int v = va; v <= vb; ++v) {
-                    const PixStage *prow = s_pix + (v - cv0) * CH_COLS + (c0 - cu0);
+                    const PixStage<A> *prow = s_pix + (v - cv0) * CH_COLS + (c0 - cu0);
 #pragma unroll
                     for (int h = 0; h < NH; ++h) {
                         if (h < nh) {
-                            const PixStage p = prow[h];
+                            const PixStage<A> p = prow[h];
                             const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
                             const float w = fminf(hi[h], fmaxf(b0, b1)) - fmaxf(lo[h], fminf(b0, b1));
-                            if (w > 0.0f) acc[j] = __builtin_fmaf(w, p.le, acc[j]);
+                            if (w > 0.0f) acc[j] = fma_acc(SQ ? w * w : w, p.le, acc[j]);
                         }
                     }
                 }

@@ -82,6 +82,9 @@ struct Scalars {
     // (e and b are stored as they are); LSQR: w uses sw.
     double sr, sp, sw;
     double x_alpha, e_alpha;         // CGLS: x += x_alpha d;  e -= e_alpha p
+    double tik_d2;                   // CGLS Tikhonov: lambda^2 * sr^2 (weight of |d_stored|^2 in NP2)
+    double damp, res2;               // LSQR damping lambda and the sum of psi^2 of its rotations
+    float tik_r, pad_f;              // CGLS Tikhonov: r = bwd_scale * A^T e - tik_r * x
     float fwd_scale, bwd_scale;      // CGLS epilogues: p = fwd_scale * (A d), r = bwd_scale * (A^T e)
     double err;
     double *history;
@@ -117,6 +120,10 @@ enum BwdEpi {
     BWD_NORM,       // out = A^T y, partial |out|^2
     BWD_LSQR0,      // out = c1 * A^T y, also z-fastest copy, partial |out|^2
     BWD_LSQR,       // out = c1 * A^T y - c2 * out, also z-fastest copy, partial |out|^2
+    BWD_TIK,        // out = bwd_scale * A^T y - tik_r * aux, partial |out|^2   (aux = x, Tikhonov)
+    BWD_JACOBI,     // out = aux * A^T y, partial aux * (A^T y)^2             (aux = 1 / diag(A^T A))
+    BWD_DIAG,       // out = sum_i w_ij^2 = diag(A^T A) (proj not read)
+    BWD_DIAG_INV,   // out = 1 / diag(A^T A), 0 where the diagonal is 0 (proj not read)
 };
 
 struct Geometry {
@@ -142,8 +149,9 @@ hipError_t launch_forward(const GeoDev &g, const TV *vol, const TV *vol_z, TP *o
 // out_z (LSQR epilogues only): receives the output in that layout as well.
 template <typename T>
 hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
-                           double *partials, const int *skip, hipStream_t st);
-int64_t forward_num_blocks(const GeoDev &g);
+                           double *partials, const int *skip, hipStream_t st, const float *aux = nullptr);
+int64_t forward_num_blocks(const GeoDev &g);                         // the default variant
+int64_t forward_num_blocks_r(const GeoDev &g, int rows_per_lane);     // rows_per_lane 1 or 2
 int64_t backward_num_blocks(const GeoDev &g);
 
 // Vector kernels (vector_ops.hip).
@@ -153,7 +161,8 @@ template <typename TS, typename TD>
 hipError_t launch_zfast_copy(const GeoDev &g, const TS *src, TD *dst, hipStream_t st);
 template <typename T>
 hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip, hipStream_t st);
-hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st);
+hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st,
+                           const double *partials2 = nullptr, int64_t nparts2 = 0);
 template <typename T>
 hipError_t launch_fill_zero(T *v, int64_t n, hipStream_t st);
 // The solvers keep the iterate x in single precision whatever the storage type
@@ -166,12 +175,50 @@ hipError_t launch_cgls_x(float *x, const T *d, const Scalars *sc, int64_t n, hip
 // d = r (+ beta d) and its z-fastest copy
 template <typename T>
 hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first,
-                         hipStream_t st);
+                         hipStream_t st, double *dpart = nullptr);
+int64_t cgls_d_num_blocks(const GeoDev &g);
 // e -= alpha p, partial |e|^2
 template <typename T>
 hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double *partials, hipStream_t st);
 // LSQR: w = w_vcoef v (init) or x += x_coef w; w = w_vcoef v - w_coef w
 template <typename T>
 hipError_t launch_lsqr_xw(float *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st);
+// forward with an explicit rows-per-lane variant (1 or 2), plain epilogue
+hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_z, float *out, int rows_per_lane,
+                            hipStream_t st);
+
+// ---------------------------------------------------------------- batched CGLS
+// One instance of a batched solve as the batched kernels see it (single
+// precision storage).  Each batched launch covers every instance: workgroup w
+// of a batched grid belongs to the instance i with off[i] <= w < off[i + 1]
+// (the per-instance grids are padded to multiples of 64 so the XCD-aware
+// workgroup orders of the single-instance kernels carry over), and runs
+// workgroup w - off[i] of that instance's own grid, with that instance's
+// partial sums and scalars; an instance whose solve has stopped skips its work.
+struct BatchInst {
+    GeoDev g;
+    int64_t n, m;               // voxels, rays
+    int fwd_r;                  // rows per lane of its forward variant
+    int nbx, nby, nbz;          // backward brick grid
+    int64_t nf, nbk;            // workgroups of its forward and backward grids (partials per launch)
+    const float *b;
+    float *x;
+    Scalars *sc;
+    double *part;
+    float *d, *dz, *r, *e, *p;
+};
+
+enum BatchGrid { BG_FWD = 0, BG_BWD, BG_DIR, BG_STREAM, BG_COUNT };  // offset tables, each count + 1 long
+
+hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st);
+hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st);
+// op: one of the batched vector steps below
+enum BatchVecOp { BV_INIT = 0, BV_NORM_B, BV_X0_E, BV_CGLS_X, BV_CGLS_E };
+hipError_t launch_batch_vec(const BatchInst *B, int count, int op, int maxiter, double err, hipStream_t st);
+hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, int64_t blocks, int first,
+                            hipStream_t st);
+// finalize of every instance; kind: which grid produced the partials (BatchGrid)
+hipError_t launch_batch_finalize(const BatchInst *B, int count, int op, int kind, hipStream_t st);
+int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz);
 
 }  // namespace kct

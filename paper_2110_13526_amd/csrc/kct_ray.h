@@ -61,11 +61,11 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
 // z-planes before t1.
 template <typename T>
 __host__ __device__ __forceinline__ void zwalk_piece(ZWalk &s, const T *__restrict__ vol, int base, int sz, int nz,
-                                                     float hz, float t0, float t1, float &acc)
+                                                     float hz, float t0, float t1, acc_t<T> &acc)
 {
     for (int guard = nz + 2; guard > 0; --guard) {
         const float w = fminf(t1, s.hzv) - fmaxf(t0, s.lz);
-        if (w > 0.0f && (unsigned)s.mz < (unsigned)nz) acc = __builtin_fmaf(w, to_f32(vol[base + s.mz * sz]), acc);
+        if (w > 0.0f && (unsigned)s.mz < (unsigned)nz) acc = fma_acc(w, to_acc(vol[base + s.mz * sz]), acc);
         if (!(s.hzv < t1)) break;
         s.lz = s.hzv;
         s.mz += s.stz;
@@ -75,7 +75,8 @@ __host__ __device__ __forceinline__ void zwalk_piece(ZWalk &s, const T *__restri
 }
 
 // Walk R rays of one detector column (rows differ, so zeta_c and czr differ)
-// through the volume and return sum_j (xi-length in voxel j) * x_j per ray.
+// through the volume and return sum_j (xi-length in voxel j) * x_j per ray, in
+// the accumulator precision of the storage type.
 //
 // The walk is split so that rays of one detector column do identical in-plane
 // work and share it:
@@ -95,10 +96,10 @@ template <typename T, int R>
 __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, int sxi, int seta, int sz, int nxi,
                                                     int neta, int nz, float hxi, float heta, float hz, float eta_c,
                                                     float inv_a, float a, const float (&zeta_c)[R],
-                                                    const float (&czr)[R], float (&acc)[R])
+                                                    const float (&czr)[R], acc_t<T> (&acc)[R])
 {
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < R; ++r) acc[r] = 0;
     // In-plane extent [t_start, t_end] of the rays inside the volume's (x, y) box.
     float lo_e, hi_e;
     if (inv_a == 0.0f) {

@@ -97,4 +97,27 @@ template <> __device__ __forceinline__ bf16 from_f32<bf16>(float v)
 }
 template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float16)v; }
 
+// Accumulator type of a storage type: single precision for the 32- and 16-bit
+// types; double for double storage, which exists so that the projector pair
+// can be evaluated to double-precision rounding (gradient checks).  The
+// weights are the same single-precision numbers in every case.
+template <typename T> struct acc_of { using type = float; };
+template <> struct acc_of<double> { using type = double; };
+template <typename T> using acc_t = typename acc_of<T>::type;
+
+__host__ __device__ __forceinline__ float to_acc(float v) { return v; }
+__device__ __forceinline__ float to_acc(bf16 v) { return to_f32(v); }
+__device__ __forceinline__ float to_acc(_Float16 v) { return (float)v; }
+__host__ __device__ __forceinline__ double to_acc(double v) { return v; }
+
+template <typename T> __device__ __forceinline__ T store_as(acc_t<T> v) { return from_f32<T>(v); }
+template <> __device__ __forceinline__ double store_as<double>(double v) { return v; }
+
+// acc + w * v with one rounding, in the accumulator's precision.
+__host__ __device__ __forceinline__ float fma_acc(float w, float v, float acc) { return __builtin_fmaf(w, v, acc); }
+__host__ __device__ __forceinline__ double fma_acc(float w, double v, double acc)
+{
+    return __builtin_fma((double)w, v, acc);
+}
+
 }  // namespace kct

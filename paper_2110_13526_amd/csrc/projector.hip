@@ -2,7 +2,7 @@
 //
 //   forward  p = A x    (Section 2, Eq. 1): ray-driven.  One lane per ray; the
 //            lanes of a wavefront hold neighbouring detector rows of one
-//            column (FWD_R rows per lane).  Their rays share the in-plane part of the walk (identical
+//            column (R rows per lane).  Their rays share the in-plane part of the walk (identical
 //            work in every lane, no divergence), differ only in z, and read a
 //            copy of the volume stored z-fastest, so one gather instruction of
 //            the wavefront touches a few neighbouring cache lines.  Each lane
@@ -12,6 +12,9 @@
 //
 // The kernel can fuse a double-precision partial sum of the squares of its
 // outputs (|p|^2 of Algorithm 1) and the LSQR bidiagonalisation update.
+#include <type_traits>
+
+#include "kct_batch.h"
 #include "kct_internal.h"
 #include "kct_ray.h"
 #include "kct_weights.h"
@@ -19,8 +22,7 @@
 namespace kct {
 
 constexpr int FWD_COLS = 4;    // detector columns per workgroup (one per wavefront)
-constexpr int FWD_R = 2;       // detector rows per lane
-constexpr int FWD_ROWS = 64 * FWD_R;  // detector rows per wavefront
+constexpr int FWD_R = 2;       // detector rows per lane (default variant; 1 is the other)
 constexpr int NXCD = 8;
 
 // Sum of v over the 256 threads of the workgroup, in a fixed order.  Result is
@@ -42,11 +44,12 @@ struct FwdGrid {
     int64_t nblocks;
 };
 
-__host__ __device__ __forceinline__ FwdGrid fwd_grid(const GeoDev &g)
+__host__ __device__ __forceinline__ FwdGrid fwd_grid(const GeoDev &g, int rows_per_lane)
 {
     FwdGrid f;
+    const int rows = 64 * rows_per_lane;  // detector rows per wavefront
     f.ncg = (g.nu + FWD_COLS - 1) / FWD_COLS;
-    f.nbands = (g.nv + FWD_ROWS - 1) / FWD_ROWS;
+    f.nbands = (g.nv + rows - 1) / rows;
     f.nviews = g.nviews;
     f.nblocks = (int64_t)f.ncg * f.nbands * f.nviews;
     return f;
@@ -57,15 +60,18 @@ __host__ __device__ __forceinline__ FwdGrid fwd_grid(const GeoDev &g)
 // volume) over many views.  Dispatch fills the eight XCDs round-robin; within
 // every 64 consecutive workgroups the order is permuted so that each XCD gets 8
 // neighbouring column groups, which share voxels in that XCD's L2.
-template <typename TV, typename TP, int EPI>
-__global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
-                                                 TP *__restrict__ out, const TP *__restrict__ aux,
-                                                 const Scalars *__restrict__ sc, double *__restrict__ partials,
-                                                 const int *__restrict__ skip)
+//
+// forward_block runs workgroup w (0 <= w < fwd_grid(g, R).nblocks) of the
+// projection of one volume; R rows per lane.  Its partial sum goes to
+// partials[w].
+template <typename TV, typename TP, int EPI, int R>
+__device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const TV *__restrict__ vol,
+                                              const TV *__restrict__ vol_z, TP *__restrict__ out,
+                                              const TP *__restrict__ aux, const Scalars *__restrict__ sc,
+                                              double *__restrict__ partials)
 {
-    if (skip && *skip) return;
-    const FwdGrid fg = fwd_grid(g);
-    const int64_t w = blockIdx.x;
+    constexpr int FWD_ROWS = 64 * R;
+    const FwdGrid fg = fwd_grid(g, R);
     const int64_t full = fg.nblocks & ~(int64_t)63;
     const int64_t L = w < full ? (w & ~(int64_t)63) + (w % NXCD) * 8 + (w / NXCD) % 8 : w;
     const int cg = (int)(L % fg.ncg);
@@ -90,13 +96,15 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict_
     }
 
     // lane rows: band * FWD_ROWS + lane + 64 r
-    float zc[FWD_R], czr[FWD_R], Ls[FWD_R], p[FWD_R];
-    bool ok[FWD_R];
+    using A = acc_t<TV>;
+    float zc[R], czr[R], Ls[R];
+    A p[R];
+    bool ok[R];
     const bool col_ok = iu < g.nu;
     ColParam cp{};
     if (col_ok) cp = g.cols[(size_t)k * g.nu + iu];
 #pragma unroll
-    for (int r = 0; r < FWD_R; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int iv = band * FWD_ROWS + lane + 64 * r;
         ok[r] = col_ok && iv < g.nv;
         const RowParam rp = ok[r] ? g.rows[iv] : RowParam{0.0f, 0.0f};
@@ -106,62 +114,123 @@ __global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict_
         if (!ok[r]) czr[r] = 1.0f, zc[r] = 3.0e30f;  // far outside: an inert ray
     }
     if (col_ok) {
-        float s[FWD_R];
-        trace_rays<TV, FWD_R>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc, czr,
+        A s[R];
+        trace_rays<TV, R>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc, czr,
                              s);
 #pragma unroll
-        for (int r = 0; r < FWD_R; ++r) p[r] = Ls[r] * s[r];
+        for (int r = 0; r < R; ++r) p[r] = (A)Ls[r] * s[r];
     } else {
 #pragma unroll
-        for (int r = 0; r < FWD_R; ++r) p[r] = 0.0f;
+        for (int r = 0; r < R; ++r) p[r] = 0;
     }
     double sq = 0.0;
 #pragma unroll
-    for (int r = 0; r < FWD_R; ++r) {
+    for (int r = 0; r < R; ++r) {
         if (!ok[r]) continue;
         const int iv = band * FWD_ROWS + lane + 64 * r;
         const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
-        float o;
-        if (EPI == FWD_BMINUS) o = to_f32(aux[ray]) - p[r];
-        else if (EPI == FWD_LSQR) o = (float)sc->fwd_c1 * p[r] - (float)sc->fwd_c2 * to_f32(out[ray]);
-        else if (EPI == FWD_NORM) o = sc->fwd_scale * p[r];
+        A o;
+        if (EPI == FWD_BMINUS) o = to_acc(aux[ray]) - p[r];
+        else if (EPI == FWD_LSQR) o = (A)sc->fwd_c1 * p[r] - (A)sc->fwd_c2 * to_acc(out[ray]);
+        else if (EPI == FWD_NORM) o = (A)sc->fwd_scale * p[r];
         else o = p[r];
-        const TP st = from_f32<TP>(o);
+        const TP st = store_as<TP>(o);
         out[ray] = st;
-        const double od = (double)to_f32(st);
+        const double od = (double)to_acc(st);
         sq += od * od;
     }
     if (EPI != FWD_PLAIN) {
         const double bs = block_sum_256(sq);
-        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+        if (threadIdx.x == 0) partials[w] = bs;
     }
 }
 
-int64_t forward_num_blocks(const GeoDev &g) { return fwd_grid(g).nblocks; }
+template <typename TV, typename TP, int EPI>
+__global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+                                                 TP *__restrict__ out, const TP *__restrict__ aux,
+                                                 const Scalars *__restrict__ sc, double *__restrict__ partials,
+                                                 const int *__restrict__ skip)
+{
+    if (skip && *skip) return;
+    forward_block<TV, TP, EPI, FWD_R>(g, blockIdx.x, vol, vol_z, out, aux, sc, partials);
+}
+
+// One explicit rows-per-lane variant, plain epilogue (the batched form's tuner times these).
+template <typename TV, typename TP, int EPI, int R>
+__global__ __launch_bounds__(256) void k_forward_r(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+                                                   TP *__restrict__ out)
+{
+    forward_block<TV, TP, EPI, R>(g, blockIdx.x, vol, vol_z, out, nullptr, nullptr, nullptr);
+}
+
+int64_t forward_num_blocks(const GeoDev &g) { return fwd_grid(g, FWD_R).nblocks; }
+int64_t forward_num_blocks_r(const GeoDev &g, int rows_per_lane) { return fwd_grid(g, rows_per_lane).nblocks; }
 
 template <typename TV, typename TP>
 hipError_t launch_forward(const GeoDev &g, const TV *vol, const TV *vol_z, TP *out, const TP *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st)
 {
-    dim3 grid((unsigned)fwd_grid(g).nblocks);
+    dim3 grid((unsigned)fwd_grid(g, FWD_R).nblocks);
     dim3 block(256);
-    switch (epi) {
-    case FWD_PLAIN:
-        hipLaunchKernelGGL((k_forward<TV, TP, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
-        break;
-    case FWD_NORM:
-        hipLaunchKernelGGL((k_forward<TV, TP, FWD_NORM>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
-        break;
-    case FWD_BMINUS:
-        hipLaunchKernelGGL((k_forward<TV, TP, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
+    if constexpr (std::is_same<TV, double>::value) {  // double storage: plain projection only
+        if (epi != FWD_PLAIN) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_forward<TV, TP, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
                            skip);
-        break;
-    case FWD_LSQR:
-        hipLaunchKernelGGL((k_forward<TV, TP, FWD_LSQR>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    } else {
+        switch (epi) {
+        case FWD_PLAIN:
+            hipLaunchKernelGGL((k_forward<TV, TP, FWD_PLAIN>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+            break;
+        case FWD_NORM:
+            hipLaunchKernelGGL((k_forward<TV, TP, FWD_NORM>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+            break;
+        case FWD_BMINUS:
+            hipLaunchKernelGGL((k_forward<TV, TP, FWD_BMINUS>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials,
+                               skip);
+            break;
+        case FWD_LSQR:
+            hipLaunchKernelGGL((k_forward<TV, TP, FWD_LSQR>), grid, block, 0, st, g, vol, vol_z, out, aux, sc, partials, skip);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_z, float *out, int rows_per_lane,
+                            hipStream_t st)
+{
+    dim3 grid((unsigned)fwd_grid(g, rows_per_lane).nblocks);
+    if (rows_per_lane == 1)
+        hipLaunchKernelGGL((k_forward_r<float, float, FWD_PLAIN, 1>), grid, dim3(256), 0, st, g, vol, vol_z, out);
+    else if (rows_per_lane == 2)
+        hipLaunchKernelGGL((k_forward_r<float, float, FWD_PLAIN, 2>), grid, dim3(256), 0, st, g, vol, vol_z, out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Batched p = A d with |p|^2 partials for every instance (CGLS steps of a
+// batched solve); each instance uses its own rows-per-lane variant.
+__global__ __launch_bounds__(256) void kb_forward(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
+                                                  int count)
+{
+    const int64_t w = blockIdx.x;
+    const int i = batch_find(off, count, w);
+    const BatchInst *bi = B + i;
+    if (bi->sc->done) return;
+    const int64_t lw = w - off[i];
+    if (lw >= fwd_grid(bi->g, bi->fwd_r).nblocks) return;  // padding of the instance's grid
+    if (bi->fwd_r == 1)
+        forward_block<float, float, FWD_NORM, 1>(bi->g, lw, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
+    else
+        forward_block<float, float, FWD_NORM, 2>(bi->g, lw, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
+}
+
+hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(kb_forward, dim3((unsigned)blocks), dim3(256), 0, st, B, off, count);
     return hipGetLastError();
 }
 
@@ -173,5 +242,6 @@ KCT_INST(bf16, bf16)
 KCT_INST(_Float16, _Float16)
 KCT_INST(float, bf16)
 KCT_INST(float, _Float16)
+KCT_INST(double, double)
 
 }  // namespace kct

@@ -9,6 +9,7 @@
 // Kernels on the iteration path take a pointer to the solver's "done" flag and
 // return at once when it is set, so a solve can be enqueued in full without
 // host synchronisation and still stop early (tolerance reached, breakdown).
+#include "kct_batch.h"
 #include "kct_internal.h"
 #include "kct_weights.h"
 
@@ -89,16 +90,19 @@ __global__ __launch_bounds__(TB) void k_cgls_e(T *__restrict__ e, const T *__res
 
 // d = r + beta d (first: d = r), and dz = d stored z-fastest.  A workgroup
 // takes a 32 (z) x 32 (x) tile of one y-plane through LDS, so the plain and
-// the z-fastest stores both coalesce.
+// the z-fastest stores both coalesce.  With dpart, also the workgroup's partial
+// sum of the stored d^2 (the Tikhonov term of NP2).
 template <typename T, int FIRST>
-__global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *__restrict__ r, T *__restrict__ d,
-                                               T *__restrict__ dz, const Scalars *__restrict__ sc)
+__device__ __forceinline__ void cgls_d_tile(int nx, int ny, int nz, const T *__restrict__ r, T *__restrict__ d,
+                                            T *__restrict__ dz, const Scalars *__restrict__ sc,
+                                            double *__restrict__ dpart, int tx_blk, int tz_blk, int y,
+                                            int64_t blk)
 {
-    if (sc->done) return;
     __shared__ float tile[32][33];
     const float beta = FIRST ? 0.0f : (float)sc->beta;
-    const int bx = blockIdx.x * 32, bz = blockIdx.y * 32, y = blockIdx.z;
+    const int bx = tx_blk * 32, bz = tz_blk * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    double sq = 0.0;
     for (int j = ty; j < 32; j += 8) {
         const int x = bx + tx, z = bz + j;
         if (x < nx && z < nz) {
@@ -108,6 +112,8 @@ __global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *
             const T st = from_f32<T>(v);
             d[i] = st;
             tile[j][tx] = to_f32(st);
+            const double dv = (double)to_f32(st);
+            sq += dv * dv;
         }
     }
     __syncthreads();
@@ -115,23 +121,37 @@ __global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *
         const int z = bz + tx, x = bx + j;
         if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = from_f32<T>(tile[tx][j]);
     }
+    if (dpart) {
+        const double b = block_sum(sq);
+        if (threadIdx.x == 0) dpart[blk] = b;
+    }
+}
+
+template <typename T, int FIRST>
+__global__ __launch_bounds__(TB) void k_cgls_d(int nx, int ny, int nz, const T *__restrict__ r, T *__restrict__ d,
+                                               T *__restrict__ dz, const Scalars *__restrict__ sc,
+                                               double *__restrict__ dpart)
+{
+    if (sc->done) return;
+    cgls_d_tile<T, FIRST>(nx, ny, nz, r, d, dz, sc, dpart, blockIdx.x, blockIdx.y, blockIdx.z,
+                          ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
 template <typename TS, typename TD>
 __global__ __launch_bounds__(TB) void k_zfast_copy(int nx, int ny, int nz, const TS *__restrict__ s,
                                                    TD *__restrict__ dz)
 {
-    __shared__ float tile[32][33];
+    __shared__ acc_t<TS> tile[32][33];
     const int bx = blockIdx.x * 32, bz = blockIdx.y * 32, y = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int j = ty; j < 32; j += 8) {
         const int x = bx + tx, z = bz + j;
-        if (x < nx && z < nz) tile[j][tx] = to_f32(s[((size_t)z * ny + y) * nx + x]);
+        if (x < nx && z < nz) tile[j][tx] = to_acc(s[((size_t)z * ny + y) * nx + x]);
     }
     __syncthreads();
     for (int j = ty; j < 32; j += 8) {
         const int z = bz + tx, x = bx + j;
-        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = from_f32<TD>(tile[tx][j]);
+        if (x < nx && z < nz) dz[((size_t)y * nx + x) * nz + z] = store_as<TD>(tile[tx][j]);
     }
 }
 
@@ -157,21 +177,33 @@ __global__ __launch_bounds__(TB) void k_lsqr_xw(float *__restrict__ x, T *__rest
 }
 
 // Fixed-order sum of the partials followed by one scalar step.
-__global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const double *__restrict__ partials,
-                                                 int64_t np, int op)
+__device__ double fixed_order_sum(const double *__restrict__ partials, int64_t np, double *red)
 {
-    if (op != F_NB0 && sc->done) return;
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < np; i += TB) s += partials[i];
-    __shared__ double red[TB];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = TB / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// One scalar step of a solve, run by one workgroup: the fixed-order sums of
+// the partials, then the step (thread 0).  partials2 (optional): a second set
+// of partials, used by F_ALPHA for the Tikhonov term |d|^2.
+__device__ __forceinline__ void finalize_step(Scalars *__restrict__ sc, const double *__restrict__ partials,
+                                              int64_t np, int op, const double *__restrict__ partials2,
+                                              int64_t np2)
+{
+    if (op != F_NB0 && sc->done) return;
+    __shared__ double red[TB];
+    const double S = fixed_order_sum(partials, np, red);
+    const double S2 = partials2 ? fixed_order_sum(partials2, np2, red) : 0.0;
     if (threadIdx.x != 0) return;
-    const double S = red[0];
     auto stop = [&](int reason) {
         sc->done = 1;
         sc->stop = reason;
@@ -196,8 +228,8 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         else if (nr2 == 0.0) stop(KCT_STOP_BREAKDOWN);
         break;
     }
-    case F_ALPHA: {  // NP2 = |p|^2, alpha = NR2_old / NP2 (p is stored divided by sp)
-        const double np2 = S * (sc->sp * sc->sp);
+    case F_ALPHA: {  // NP2 = |p|^2 (+ lambda^2 |d|^2), alpha = NR2_old / NP2 (p is stored divided by sp)
+        const double np2 = S * (sc->sp * sc->sp) + sc->tik_d2 * S2;
         sc->np2 = np2;
         if (!isfinite(np2)) stop(KCT_STOP_NUMERIC);
         else if (np2 == 0.0) stop(KCT_STOP_BREAKDOWN);
@@ -267,7 +299,14 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
         const double a = sc->skip_bwd ? 0.0 : sqrt(S);
         sc->nr2_now = a * a;
         if (!isfinite(a)) { stop(KCT_STOP_NUMERIC); break; }
-        // Givens rotation (Paige & Saunders)
+        // damping rotation (Tikhonov term), then the Givens rotation (Paige & Saunders)
+        if (sc->damp != 0.0) {
+            const double rhobar1 = sqrt(sc->rhobar * sc->rhobar + sc->damp * sc->damp);
+            const double psi = (sc->damp / rhobar1) * sc->phibar;
+            sc->res2 += psi * psi;
+            sc->phibar = (sc->rhobar / rhobar1) * sc->phibar;
+            sc->rhobar = rhobar1;
+        }
         const double beta = sc->l_beta;
         const double rho = sqrt(sc->rhobar * sc->rhobar + beta * beta);
         const double c = sc->rhobar / rho, s = beta / rho;
@@ -289,7 +328,7 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
     }
     case F_L_GIVENS: {  // after x and w are updated: i = i + 1, stop tests
         sc->iters += 1;
-        const double nb = fabs(sc->phibar);
+        const double nb = sqrt(sc->phibar * sc->phibar + sc->res2);  // |phibar| without damping
         sc->nb = nb;
         if (sc->history) sc->history[sc->iters - 1] = sc->nb0 > 0.0 ? nb / sc->nb0 : 0.0;
         if (!isfinite(nb)) stop(KCT_STOP_NUMERIC);
@@ -301,6 +340,109 @@ __global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const
     default:
         break;
     }
+}
+
+__global__ __launch_bounds__(TB) void k_finalize(Scalars *__restrict__ sc, const double *__restrict__ partials,
+                                                 int64_t np, int op, const double *__restrict__ partials2,
+                                                 int64_t np2)
+{
+    finalize_step(sc, partials, np, op, partials2, np2);
+}
+
+// ---------------------------------------------------------------- batched
+// Batched streaming steps: workgroup w serves instance w / STREAM_BLOCKS as
+// workgroup w % STREAM_BLOCKS of that instance's own streaming grid, so every
+// instance sees the block decomposition (and the partial sums) of a single solve.
+__global__ __launch_bounds__(TB) void kb_vec(const BatchInst *__restrict__ B, int op, int maxiter, double err)
+{
+    const int i = blockIdx.x / STREAM_BLOCKS;
+    const int lb = blockIdx.x % STREAM_BLOCKS;
+    const BatchInst *bi = B + i;
+    Scalars *sc = bi->sc;
+    const int64_t stride = (int64_t)STREAM_BLOCKS * TB;
+    const int64_t i0 = (int64_t)lb * TB + threadIdx.x;
+    if (op == BV_INIT) {  // scalars of a plain FP32 CGLS solve (all storage scales 1)
+        if (lb == 0 && threadIdx.x == 0) {
+            Scalars s;
+            memset(&s, 0, sizeof(s));
+            s.maxiter = maxiter;
+            s.err = err;
+            s.sr = s.sp = s.sw = 1.0;
+            s.fwd_scale = s.bwd_scale = 1.0f;
+            *sc = s;
+        }
+        return;
+    }
+    if (op == BV_NORM_B) {  // partials of |b|^2
+        double q = 0.0;
+        for (int64_t k = i0; k < bi->m; k += stride) {
+            const double v = (double)bi->b[k];
+            q += v * v;
+        }
+        const double bs = block_sum(q);
+        if (threadIdx.x == 0) bi->part[lb] = bs;
+        return;
+    }
+    if (sc->done) return;
+    if (op == BV_X0_E) {  // x0 = 0, e = b
+        for (int64_t k = i0; k < bi->n; k += stride) bi->x[k] = 0.0f;
+        for (int64_t k = i0; k < bi->m; k += stride) bi->e[k] = bi->b[k];
+    } else if (op == BV_CGLS_X) {  // x += alpha d
+        const float alpha = (float)sc->x_alpha;
+        for (int64_t k = i0; k < bi->n; k += stride) bi->x[k] = bi->x[k] + alpha * bi->d[k];
+    } else if (op == BV_CGLS_E) {  // e -= alpha p, partials of |e|^2
+        const float alpha = (float)sc->e_alpha;
+        double q = 0.0;
+        for (int64_t k = i0; k < bi->m; k += stride) {
+            const float v = bi->e[k] - alpha * bi->p[k];
+            bi->e[k] = v;
+            q += (double)v * (double)v;
+        }
+        const double bs = block_sum(q);
+        if (threadIdx.x == 0) bi->part[lb] = bs;
+    }
+}
+
+template <int FIRST>
+__global__ __launch_bounds__(TB) void kb_dir(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
+                                             int count)
+{
+    const int64_t w = blockIdx.x;
+    const int i = batch_find(off, count, w);
+    const BatchInst *bi = B + i;
+    if (bi->sc->done) return;
+    const int gx = (bi->g.nx + 31) / 32, gz = (bi->g.nz + 31) / 32;
+    const int64_t lw = w - off[i];
+    if (lw >= (int64_t)gx * gz * bi->g.ny) return;
+    cgls_d_tile<float, FIRST>(bi->g.nx, bi->g.ny, bi->g.nz, bi->r, bi->d, bi->dz, bi->sc, nullptr, (int)(lw % gx),
+                              (int)((lw / gx) % gz), (int)(lw / ((int64_t)gx * gz)), lw);
+}
+
+__global__ __launch_bounds__(TB) void kb_finalize(const BatchInst *__restrict__ B, int op, int kind)
+{
+    const BatchInst *bi = B + blockIdx.x;
+    const int64_t np = kind == BG_FWD ? bi->nf : (kind == BG_BWD ? bi->nbk : (int64_t)STREAM_BLOCKS);
+    finalize_step(bi->sc, bi->part, np, op, nullptr, 0);
+}
+
+hipError_t launch_batch_vec(const BatchInst *B, int count, int op, int maxiter, double err, hipStream_t st)
+{
+    hipLaunchKernelGGL(kb_vec, dim3((unsigned)(count * STREAM_BLOCKS)), dim3(TB), 0, st, B, op, maxiter, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, int64_t blocks, int first,
+                            hipStream_t st)
+{
+    if (first) hipLaunchKernelGGL(kb_dir<1>, dim3((unsigned)blocks), dim3(TB), 0, st, B, off, count);
+    else hipLaunchKernelGGL(kb_dir<0>, dim3((unsigned)blocks), dim3(TB), 0, st, B, off, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchInst *B, int count, int op, int kind, hipStream_t st)
+{
+    hipLaunchKernelGGL(kb_finalize, dim3((unsigned)count), dim3(TB), 0, st, B, op, kind);
+    return hipGetLastError();
 }
 
 static dim3 sgrid(int64_t n)
@@ -327,9 +469,10 @@ hipError_t launch_norm2(const T *v, int64_t n, double *partials, const int *skip
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st)
+hipError_t launch_finalize(Scalars *sc, const double *partials, int64_t nparts, int op, hipStream_t st,
+                           const double *partials2, int64_t nparts2)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TB), 0, st, sc, partials, nparts, op);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(TB), 0, st, sc, partials, nparts, op, partials2, nparts2);
     return hipGetLastError();
 }
 
@@ -355,13 +498,16 @@ hipError_t launch_cgls_x(float *x, const T *d, const Scalars *sc, int64_t n, hip
 }
 
 template <typename T>
-hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first, hipStream_t st)
+hipError_t launch_cgls_d(const GeoDev &g, const T *r, T *d, T *dz, const Scalars *sc, int first, hipStream_t st,
+                         double *dpart)
 {
     dim3 grid((g.nx + 31) / 32, (g.nz + 31) / 32, g.ny);
-    if (first) hipLaunchKernelGGL((k_cgls_d<T, 1>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc);
-    else hipLaunchKernelGGL((k_cgls_d<T, 0>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc);
+    if (first) hipLaunchKernelGGL((k_cgls_d<T, 1>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc, dpart);
+    else hipLaunchKernelGGL((k_cgls_d<T, 0>), grid, dim3(TB), 0, st, g.nx, g.ny, g.nz, r, d, dz, sc, dpart);
     return hipGetLastError();
 }
+
+int64_t cgls_d_num_blocks(const GeoDev &g) { return (int64_t)((g.nx + 31) / 32) * ((g.nz + 31) / 32) * g.ny; }
 
 template <typename T>
 hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double *partials, hipStream_t st)
@@ -384,7 +530,7 @@ hipError_t launch_lsqr_xw(float *x, T *w, const T *v, const Scalars *sc, int ini
     template hipError_t launch_copy<T>(const T *, T *, int64_t, hipStream_t);                             \
     template hipError_t launch_cgls_x<T>(float *, const T *, const Scalars *, int64_t, hipStream_t);      \
     template hipError_t launch_cgls_d<T>(const GeoDev &, const T *, T *, T *, const Scalars *, int,       \
-                                         hipStream_t);                                                    \
+                                         hipStream_t, double *);                                          \
     template hipError_t launch_cgls_e<T>(T *, const T *, const Scalars *, int64_t, double *, hipStream_t); \
     template hipError_t launch_lsqr_xw<T>(float *, T *, const T *, const Scalars *, int, int64_t, hipStream_t);
 KCT_VINST(float)
@@ -395,5 +541,6 @@ KCT_VINST(_Float16)
 KCT_ZINST(float, float)
 KCT_ZINST(bf16, bf16)
 KCT_ZINST(_Float16, _Float16)
+KCT_ZINST(double, double)
 
 }  // namespace kct

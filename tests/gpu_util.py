@@ -23,7 +23,9 @@ def to_dev(a, dtype=None):
 
 
 def to_np(t):
-    return t.detach().float().cpu().numpy().astype(np.float64)
+    """float64 numpy copy (exact for every storage type, float64 included)."""
+    torch = torch_mod()
+    return t.detach().to(torch.float64).cpu().numpy()
 
 
 def geometry(desc):

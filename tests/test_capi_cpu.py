@@ -4,6 +4,7 @@ import os
 import re
 
 import numpy as np
+import pytest
 
 import kct_inputs as ki
 
@@ -43,13 +44,36 @@ def test_product_does_not_use_the_oracle():
                 assert "kct_oracle" not in text and "libkct_oracle" not in text, f
 
 
-def test_struct_layouts_match_header():
-    """ctypes mirrors of the C structs have the sizes of their C definitions (x86-64 ABI)."""
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the C structs have the size and field offsets that
+    a C compiler gives the definitions in include/kct.h."""
+    import shutil
+    import subprocess
     from paper_2110_13526_amd import _lib
-    assert ctypes.sizeof(_lib.VolumeDesc) == 3 * 4 + 4 + 6 * 8
-    assert ctypes.sizeof(_lib.ConeDesc) == 4 + 4 + 2 * 8 + 8 + 2 * 8 + 2 * 4 + 4 * 8
-    assert ctypes.sizeof(_lib.SolveOpts) == 4 + 4 + 8 + 4 + 4 + 8
-    assert ctypes.sizeof(_lib.SolveInfo) == 4 + 4 + 3 * 8 + 4 + 4
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"kct_volume_desc": _lib.VolumeDesc, "kct_cone_desc": _lib.ConeDesc,
+               "kct_solve_opts": _lib.SolveOpts, "kct_solve_info": _lib.SolveInfo}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "kct.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+                    str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_phantom_recipe():

@@ -11,8 +11,14 @@ which bounds the relative L2 error of the whole vector by the same amount.
 
 Solver tolerances are empirical: every iteration rounds r, d, p and e (CGLS)
 or u, v and w (LSQR) to the storage type, and those perturbations propagate
-through the recurrences; the bound used is about four times the error
-measured on the c1 problem, and the FP32 form is checked at the same time.
+through the recurrences; the bound used is about four times the largest error
+measured on the c1 problem (x and discrepancy history after 10 iterations:
+BF16 3.1e-3 / 4.3e-3, FP16 3.8e-4 / 4.6e-5), and the FP32 form is checked at
+the same time with the FP32 bound 1e-4.
+
+Double storage (float64 tensors) accumulates in double precision over the
+same single-precision weights: against the oracle it carries the FP32 weight
+bound 1e-5, and its adjoint identity holds to double rounding.
 """
 import numpy as np
 import pytest
@@ -95,7 +101,7 @@ def c1_problem():
     return g, geometry(g), x_true, b
 
 
-SOLVE_TOL = {"f32": 1e-4, "bf16": 2e-2, "f16": 4e-3}
+SOLVE_TOL = {"f32": 1e-4, "bf16": 1.5e-2, "f16": 1.5e-3}
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16", "f16"])
@@ -172,3 +178,33 @@ def test_precision_report_c3down():
     assert report["f32"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["f32"]
     assert report["bf16"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["bf16"]
     assert report["f16"]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL["f16"]
+
+
+def test_f64_projector_pair():
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g = ki.t16("offcenter")
+    G = geometry(g)
+    say("[precision] f64 projector")
+    rng = np.random.default_rng(21)
+    x = ki.phantom(g, 10, 7).astype(np.float64)
+    y = np.abs(rng.standard_normal(g.proj_shape))
+    xd = torch.from_numpy(x).to(dev())
+    yd = torch.from_numpy(y).to(dev())
+    b = kct.project(G, xd)
+    r = kct.backproject(G, yd)
+    assert b.dtype == torch.float64 and r.dtype == torch.float64
+    assert rel(to_np(b), oracle.project(g, x)) < ACC_TOL
+    assert rel(to_np(r), oracle.backproject(g, y)) < ACC_TOL
+    # the same matrix both ways, summed in double precision
+    xr = rng.standard_normal(g.vol_shape)
+    yr = rng.standard_normal(g.proj_shape)
+    lhs = float((kct.project(G, torch.from_numpy(xr).to(dev())).cpu().numpy() * yr).sum())
+    rhs = float((xr * kct.backproject(G, torch.from_numpy(yr).to(dev())).cpu().numpy()).sum())
+    say(f"  adjoint rel {abs(lhs - rhs) / abs(lhs):.3e}")
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    # transposed-copy and in-place reads give the same bits
+    assert torch.equal(kct.project(G, xd, transposed_copy=False), b)
+    # the solvers do not take double storage
+    with pytest.raises(kct.KctError):
+        kct.cgls(G, yd, 2)

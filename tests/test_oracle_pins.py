@@ -8,6 +8,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 import kct_inputs as ki
@@ -317,3 +318,85 @@ def test_cgls_edge_cases():
     assert res.stop_reason == oracle.STOP_TOL and res.history[-1] <= 0.2 and res.iterations < 50
     res = oracle.lsqr(g, b, 50, err=0.2)
     assert res.stop_reason == oracle.STOP_TOL and res.history[-1] <= 0.2 and res.iterations < 50
+
+
+# ------------------------------------------------- variants (Sections 3, 5, 7)
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "aniso", "odd"])
+def test_diag_normal_is_squared_column_norms(variant):
+    """diag(A^T A)_j = sum_i w_ij^2, against the brute-force matrix."""
+    g = ki.t16(variant)
+    A = bf.matrix(g)
+    ref = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+    assert rel(oracle.diag_normal(g).ravel(), ref) < 1e-12
+
+
+@pytest.mark.parametrize("K", [3, 8])
+@pytest.mark.parametrize("lam", [0.5, 3.0])
+def test_tikhonov_cgls_and_damped_lsqr_match_scipy(small_problem, K, lam):
+    """min |b - A x|^2 + lambda^2 |x|^2: scipy's LSQR with damp, the oracle's damped
+    LSQR and the oracle's CGLS on [A; lambda I] give the same K-th iterate."""
+    g, A, b = small_problem
+    ref = spla.lsqr(A, b.ravel(), damp=lam, atol=0.0, btol=0.0, conlim=0.0, iter_lim=K)[0]
+    rl = oracle.lsqr(g, b, K, damp=lam)
+    rc = oracle.cgls(g, b, K, tikhonov=lam)
+    assert rel(rl.x, ref) < 1e-8
+    assert rel(rc.x, ref) < 1e-8
+    # LSQR's residual estimate is the stacked residual, CGLS's NB the data residual
+    x = rl.x.ravel()
+    stacked = np.sqrt(np.linalg.norm(b.ravel() - A @ x) ** 2 + lam ** 2 * np.linalg.norm(x) ** 2)
+    assert abs(rl.nb - stacked) <= 1e-9 * stacked
+    assert abs(rc.nb - np.linalg.norm(b.ravel() - A @ rc.x.ravel())) <= 1e-9 * rc.nb
+
+
+def test_tikhonov_cgls_converges_to_regularised_solution(small_problem):
+    """With a strong penalty the normal matrix A^T A + lambda^2 I is well conditioned
+    and the iterate reaches the dense solution of the regularised normal equations."""
+    g, A, b = small_problem
+    lam = 4.0
+    Ad = A.toarray()
+    ref = np.linalg.solve(Ad.T @ Ad + lam ** 2 * np.eye(Ad.shape[1]), Ad.T @ b.ravel())
+    assert rel(oracle.cgls(g, b, 80, tikhonov=lam).x, ref) < 1e-9
+    assert rel(oracle.lsqr(g, b, 80, damp=lam).x, ref) < 1e-9
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_recomputed_discrepancy_gives_the_same_iterates(small_problem, every):
+    """Recomputing e = b - A x every k iterations instead of updating it changes
+    nothing in exact arithmetic (Section 5: the drift is below 1e-6)."""
+    g, A, b = small_problem
+    r0 = oracle.cgls(g, b, 10)
+    r1 = oracle.cgls(g, b, 10, recompute_every=every)
+    assert rel(r1.x, r0.x) < 1e-10
+    np.testing.assert_allclose(r1.history, r0.history, rtol=1e-9)
+
+
+def krylov_minimiser_jacobi(A, b, x0, K, M):
+    """argmin |b - A x| over x0 + M span{r0, (M A^T A M) r0, ...}, r0 = M A^T (b - A x0)."""
+    AM = A @ sp.diags(M)
+    z = krylov_minimiser(AM, b - A @ x0, np.zeros(A.shape[1]), K)
+    return x0 + M * z
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 6])
+def test_jacobi_cgls_is_preconditioned_krylov_minimiser(small_problem, K):
+    g, A, b = small_problem
+    dg = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+    M = np.where(dg > 0, 1.0 / np.sqrt(np.where(dg > 0, dg, 1.0)), 0.0)
+    x0 = ki.random_volume(g, 35).ravel() * 0.05
+    assert rel(oracle.cgls_jacobi(g, b, K, x0=x0).x.ravel(), krylov_minimiser_jacobi(A, b.ravel(), x0, K, M)) < 1e-9
+    # and the same iterate as scipy's LSQR on A M
+    z = spla.lsqr(A @ sp.diags(M), b.ravel(), atol=0.0, btol=0.0, conlim=0.0, iter_lim=K)[0]
+    assert rel(oracle.cgls_jacobi(g, b, K).x.ravel(), M * z) < 1e-8
+
+
+def test_tikhonov_cgls_with_initial_guess(small_problem):
+    """With x0 the Tikhonov CGLS is CGLS on the stacked system [A; lambda I] x = [b; 0]
+    started at x0: scipy's LSQR on the explicitly stacked matrix gives the same iterate."""
+    g, A, b = small_problem
+    lam, K = 1.5, 5
+    x0 = ki.random_volume(g, 36).ravel() * 0.05
+    S = sp.vstack([A, lam * sp.identity(A.shape[1], format="csr")]).tocsr()
+    rhs = np.concatenate([b.ravel(), np.zeros(A.shape[1])])
+    ref = spla.lsqr(S, rhs, atol=0.0, btol=0.0, conlim=0.0, iter_lim=K, x0=x0)[0]
+    assert rel(oracle.cgls(g, b, K, x0=x0, tikhonov=lam).x.ravel(), ref) < 1e-8
