@@ -107,6 +107,23 @@ kct_status kct_geometry_create(const kct_volume_desc *vol, const kct_cone_desc *
  * still uses the geometry. */
 void kct_geometry_destroy(kct_geometry g);
 
+/* Projector models (Section 3).  KCT_PROJECTOR_SIDDON (the default): w_ij is
+ * the length of ray i inside voxel j.  KCT_PROJECTOR_TT: the separable
+ * footprint model with trapezoid transaxial and trapezoid axial footprints
+ * (the projector of the paper's experiments, Section 4):
+ * w_ij = L_i F_u F_v, F_u and F_v the pixel means of unit trapezoids whose
+ * breakpoints are the detector coordinates of the voxel's in-plane corners
+ * (transaxial) and of its z extent seen from its nearest and farthest in-plane
+ * corner (axial), L_i = min(vx/|d_x|, vy/|d_y|, vz/|d_z|) for ray i's unit
+ * direction d.  Both pairs evaluate identical weights in the projector and the
+ * backprojector. */
+enum { KCT_PROJECTOR_SIDDON = 0, KCT_PROJECTOR_TT = 1 };
+
+/* Select the projector model used by every later call with g (project,
+ * backproject, diag_normal, the solvers).  Batched solves take Siddon
+ * geometries only.  Errors: INVALID_ARG. */
+kct_status kct_geometry_set_projector(kct_geometry g, int32_t projector);
+
 /* Number of voxels (n) and rays (m) of A in R^{m x n} (Section 2, Eq. 1). */
 kct_status kct_geometry_dims(kct_geometry g, int64_t *n_vox, int64_t *n_rays);
 

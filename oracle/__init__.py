@@ -69,15 +69,21 @@ def lib():
                                         dp, dp, dp, ip]
         L.oracle_lsqr.restype = ctypes.c_int
         L.oracle_cgls_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, ip]
         L.oracle_cgls_ex.restype = ctypes.c_int
         L.oracle_lsqr_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           ctypes.c_double, dp, dp, dp, ip]
+                                           ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
         L.oracle_lsqr_ex.restype = ctypes.c_int
         L.oracle_diag_normal.argtypes = geo + [dp]
         L.oracle_diag_normal.restype = None
         L.oracle_cgls_jacobi.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
         L.oracle_cgls_jacobi.restype = ctypes.c_int
+        L.oracle_tt_project.argtypes = geo + [dp, dp]
+        L.oracle_tt_project.restype = None
+        L.oracle_tt_backproject.argtypes = geo + [dp, dp]
+        L.oracle_tt_backproject.restype = None
+        L.oracle_tt_diag_normal.argtypes = geo + [dp]
+        L.oracle_tt_diag_normal.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
@@ -182,11 +188,15 @@ class SolveResult:
         return f"SolveResult(iterations={self.iterations}, nb={self.nb:.6g}, stop={self.stop_reason})"
 
 
-def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0):
+PROJECTORS = {"siddon": 0, "tt": 1}
+
+
+def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0, projector="siddon"):
     """Algorithm 1 (CGLS with delayed residual) in FP64.
 
     tikhonov = lambda adds lambda^2 |x|^2 to the objective (CGLS on [A; lambda I]);
-    recompute_every = k > 0 recomputes e = b - A x after every k-th iteration."""
+    recompute_every = k > 0 recomputes e = b - A x after every k-th iteration;
+    projector "siddon" or "tt" selects the operator."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
@@ -194,13 +204,14 @@ def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recomput
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
     stop = lib().oracle_cgls_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                                int(bool(literal_update)), float(tikhonov), int(recompute_every), _ptr(hist),
+                                int(bool(literal_update)), float(tikhonov), int(recompute_every),
+                                PROJECTORS[projector], _ptr(hist),
                                 ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 
 
-def lsqr(g, b, K, x0=None, err=0.0, damp=0.0):
+def lsqr(g, b, K, x0=None, err=0.0, damp=0.0, projector="siddon"):
     """LSQR (Paige & Saunders) in FP64, iterations aligned with CGLS.
 
     damp = lambda > 0 solves min |b - A x|^2 + lambda^2 |x - x0|^2."""
@@ -211,7 +222,8 @@ def lsqr(g, b, K, x0=None, err=0.0, damp=0.0):
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
     stop = lib().oracle_lsqr_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                                float(damp), _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
+                                float(damp), PROJECTORS[projector], _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0),
+                                ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 
@@ -236,6 +248,32 @@ def cgls_jacobi(g, b, K, x0=None, err=0.0):
                                     _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
+
+
+def tt_project(g, x):
+    """b = A_TT x, the trapezoid-trapezoid footprint projector, FP64."""
+    gt = _geo(g)
+    x = _vol(g, x)
+    b = np.zeros(g.n_views * g.nv * g.nu)
+    lib().oracle_tt_project(*_gargs(gt), _ptr(x), _ptr(b))
+    return b.reshape(g.n_views, g.nv, g.nu)
+
+
+def tt_backproject(g, y):
+    """r = A_TT^T y, FP64."""
+    gt = _geo(g)
+    y = _proj(g, y)
+    r = np.zeros(g.nx * g.ny * g.nz)
+    lib().oracle_tt_backproject(*_gargs(gt), _ptr(y), _ptr(r))
+    return r.reshape(g.nz, g.ny, g.nx)
+
+
+def tt_diag_normal(g):
+    """diag(A_TT^T A_TT) = sum_i a_ij^2 per voxel, FP64."""
+    gt = _geo(g)
+    out = np.zeros(g.nx * g.ny * g.nz)
+    lib().oracle_tt_diag_normal(*_gargs(gt), _ptr(out))
+    return out.reshape(g.nz, g.ny, g.nx)
 
 
 def num_threads():

@@ -36,6 +36,9 @@
  *             with Paige & Saunders' damping), the diagonal of A^T A and
  *             Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)),
  *             and CGLS with the discrepancy recomputed every k iterations.
+ *   A_TT   -- the separable trapezoid-footprint model named in Section 3 (the
+ *             projector of the experiments in Section 4), with its adjoint and
+ *             squared-weight sums; CGLS and LSQR run on either operator.
  *
  * Geometry convention (the paper gives only SID, SDD, pixel size and the number
  * of angles, Section 4): right-handed world frame in mm, rotation axis +z,
@@ -508,12 +511,31 @@ enum { OG_STOP_MAXITER = 0, OG_STOP_TOL = 1, OG_STOP_BREAKDOWN = 2, OG_STOP_NUME
  * NR2 = 0 or NP2 = 0 is a breakdown that stops with the current x.
  * literal_update = 1 uses the printed direction update d = d + beta r.
  */
+void oracle_tt_project(const int32_t *dims, const double *par, const double *angles, const double *x, double *b);
+void oracle_tt_backproject(const int32_t *dims, const double *par, const double *angles, const double *y, double *r);
+
+/* The operator of a solve: the Siddon pair (projector 0) or the TT pair (1). */
+static void og_A(int projector, const int32_t *dims, const double *par, const double *angles, const double *x,
+                 double *b)
+{
+    if (projector == 1) oracle_tt_project(dims, par, angles, x, b);
+    else oracle_project(dims, par, angles, x, b);
+}
+
+static void og_AT(int projector, const int32_t *dims, const double *par, const double *angles, const double *y,
+                  double *r)
+{
+    if (projector == 1) oracle_tt_backproject(dims, par, angles, y, r);
+    else oracle_backproject(dims, par, angles, y, r);
+}
+
 /* e = e - alpha p (the update of Algorithm 1), or e = b - A x when recompute. */
-static void og_cgls_discrepancy(const int32_t *dims, const double *par, const double *angles, const double *b,
-                                const double *x, double *e, double *p, double alpha, int64_t m, int recompute)
+static void og_cgls_discrepancy(int projector, const int32_t *dims, const double *par, const double *angles,
+                                const double *b, const double *x, double *e, double *p, double alpha, int64_t m,
+                                int recompute)
 {
     if (recompute) {
-        oracle_project(dims, par, angles, x, p);
+        og_A(projector, dims, par, angles, x, p);
         for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
     } else {
         for (int64_t t = 0; t < m; ++t) e[t] -= alpha * p[t];
@@ -531,7 +553,7 @@ static void og_cgls_discrepancy(const int32_t *dims, const double *par, const do
  */
 int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
                    const double *b, double *x, int K, double err, int x0_is_zero,
-                   int literal_update, double lambda, int recompute_every, double *history,
+                   int literal_update, double lambda, int recompute_every, int projector, double *history,
                    double *out_nb, double *out_nb0, int *out_iters)
 {
     const double l2 = lambda * lambda;
@@ -550,29 +572,29 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
     if (x0_is_zero) memset(x, 0, sizeof(double) * (size_t)n);
     /* p = A x ; e = b - p */
     if (x0_is_zero) memset(p, 0, sizeof(double) * (size_t)m);
-    else oracle_project(dims, par, angles, x, p);
+    else og_A(projector, dims, par, angles, x, p);
     for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
     NB = sqrt(og_dot(e, e, m));
     /* r = A^T e - lambda^2 x ; d = r ; NR2_old = |r|^2 */
-    oracle_backproject(dims, par, angles, e, r);
+    og_AT(projector, dims, par, angles, e, r);
     if (l2 != 0.0)
         for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
     memcpy(d, r, sizeof(double) * (size_t)n);
     double NR2_old = og_dot(r, r, n);
     if (NR2_old == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     /* p = A d ; NP2 = |p|^2 + lambda^2 |d|^2 ; alpha ; x += alpha d ; e -= alpha p ; NB */
-    oracle_project(dims, par, angles, d, p);
+    og_A(projector, dims, par, angles, d, p);
     double NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
     if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     double alpha = NR2_old / NP2;
     for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
     i = 1;
-    og_cgls_discrepancy(dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+    og_cgls_discrepancy(projector, dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
     NB = sqrt(og_dot(e, e, m));
     if (history) history[0] = NB0 > 0 ? NB / NB0 : 0.0;
     if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
     while (NB > err * NB0 && i < K) {
-        oracle_backproject(dims, par, angles, e, r);
+        og_AT(projector, dims, par, angles, e, r);
         if (l2 != 0.0)
             for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
         double NR2_now = og_dot(r, r, n);
@@ -583,13 +605,13 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
         else
             for (int64_t t = 0; t < n; ++t) d[t] = r[t] + beta * d[t];
         NR2_old = NR2_now;
-        oracle_project(dims, par, angles, d, p);
+        og_A(projector, dims, par, angles, d, p);
         NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
         if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         alpha = NR2_old / NP2;
         for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
         i = i + 1;
-        og_cgls_discrepancy(dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+        og_cgls_discrepancy(projector, dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
         NB = sqrt(og_dot(e, e, m));
         if (history) history[i - 1] = NB0 > 0 ? NB / NB0 : 0.0;
         if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
@@ -675,7 +697,7 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
                 int literal_update, double *history, double *out_nb, double *out_nb0,
                 int *out_iters)
 {
-    return oracle_cgls_ex(dims, par, angles, b, x, K, err, x0_is_zero, literal_update, 0.0, 0, history, out_nb,
+    return oracle_cgls_ex(dims, par, angles, b, x, K, err, x0_is_zero, literal_update, 0.0, 0, 0, history, out_nb,
                           out_nb0, out_iters);
 }
 
@@ -699,7 +721,7 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
  * stacked residual [b - A x; -lambda (x - x0)] (|phibar| when lambda = 0).
  */
 int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
-                   const double *b, double *x, int K, double err, int x0_is_zero, double damp,
+                   const double *b, double *x, int K, double err, int x0_is_zero, double damp, int projector,
                    double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
     og_t g = og_make(dims, par, angles);
@@ -717,14 +739,14 @@ int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
     if (x0_is_zero) memset(x, 0, sizeof(double) * (size_t)n);
     if (x0_is_zero) memcpy(u, b, sizeof(double) * (size_t)m);
     else {
-        oracle_project(dims, par, angles, x, tmpm);
+        og_A(projector, dims, par, angles, x, tmpm);
         for (int64_t t = 0; t < m; ++t) u[t] = b[t] - tmpm[t];
     }
     double beta = sqrt(og_dot(u, u, m));
     phibar = beta;
     if (beta == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     for (int64_t t = 0; t < m; ++t) u[t] /= beta;
-    oracle_backproject(dims, par, angles, u, v);
+    og_AT(projector, dims, par, angles, u, v);
     double alpha = sqrt(og_dot(v, v, n));
     if (alpha == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     for (int64_t t = 0; t < n; ++t) v[t] /= alpha;
@@ -732,7 +754,7 @@ int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
     double rhobar = alpha;
     while (i < K) {
         /* bidiagonalisation: beta u = A v - alpha u */
-        oracle_project(dims, par, angles, v, tmpm);
+        og_A(projector, dims, par, angles, v, tmpm);
         for (int64_t t = 0; t < m; ++t) u[t] = tmpm[t] - alpha * u[t];
         beta = sqrt(og_dot(u, u, m));
         int last = (i + 1 == K);
@@ -741,7 +763,7 @@ int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
             for (int64_t t = 0; t < m; ++t) u[t] /= beta;
             if (!last) {
                 /* alpha v = A^T u - beta v */
-                oracle_backproject(dims, par, angles, u, tmpn);
+                og_AT(projector, dims, par, angles, u, tmpn);
                 for (int64_t t = 0; t < n; ++t) v[t] = tmpn[t] - beta * v[t];
                 alpha_next = sqrt(og_dot(v, v, n));
                 if (alpha_next != 0.0)
@@ -785,7 +807,209 @@ int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
                 const double *b, double *x, int K, double err, int x0_is_zero,
                 double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
-    return oracle_lsqr_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0.0, history, out_nb, out_nb0, out_iters);
+    return oracle_lsqr_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0.0, 0, history, out_nb, out_nb0, out_iters);
+}
+
+/* ---------------------------------------------------------------- TT footprint projector
+ *
+ * The separable-footprint projector with trapezoid transaxial and trapezoid
+ * axial footprints (Section 3 names footprint methods after Long et al. 2010;
+ * the experiments of Section 4 use the TT variant).  The paper gives no
+ * formulas; the reading implemented here:
+ *   a_ij = L_i * F_u(i, j) * F_v(i, j), where
+ *   F_u  is the mean, over the extent of ray i's detector column, of the
+ *        unit-height trapezoid whose breakpoints are the detector u-coordinates
+ *        of the four in-plane corners of voxel j (its exact transaxial shadow,
+ *        with linear ramps);
+ *   F_v  is the same along v, with breakpoints v(z_lo, D_min), v(z_lo, D_max),
+ *        v(z_hi, D_min), v(z_hi, D_max): the voxel's z extent seen from the
+ *        nearest and the farthest of its in-plane corners (depths D along the
+ *        central ray);
+ *   L_i  is the length of the longest chord of a voxel parallel to ray i,
+ *        min(vx / |d_x|, vy / |d_y|, vz / |d_z|) for the unit direction d of ray i
+ *        (source -> pixel centre).
+ * The trapezoids of neighbouring voxels share breakpoints and have
+ * complementary ramps, so they sum to one across a row of voxels.
+ */
+
+/* Integral of the unit trapezoid t[0] <= t[1] <= t[2] <= t[3] from -inf to u. */
+static double tt_cum(const double t[4], double u)
+{
+    if (u <= t[0]) return 0.0;
+    double g = 0.0;
+    if (u < t[1]) return (u - t[0]) * (u - t[0]) / (2.0 * (t[1] - t[0]));
+    g += 0.5 * (t[1] - t[0]);
+    if (u < t[2]) return g + (u - t[1]);
+    g += t[2] - t[1];
+    if (u < t[3]) return g + 0.5 * (t[3] - t[2]) - (t[3] - u) * (t[3] - u) / (2.0 * (t[3] - t[2]));
+    return g + 0.5 * (t[3] - t[2]);
+}
+
+static void tt_sort4(double t[4])
+{
+    for (int i = 1; i < 4; ++i)
+        for (int j = i; j > 0 && t[j] < t[j - 1]; --j) {
+            double h = t[j]; t[j] = t[j - 1]; t[j - 1] = h;
+        }
+}
+
+/* Transaxial breakpoints (mm on the detector u axis, sorted) of voxel column
+ * (ix, iy) in view k, and the smallest / largest depth of its corners. */
+static void tt_transaxial(const og_t *g, int k, int ix, int iy, double tu[4], double *dmin, double *dmax)
+{
+    double c = cos(g->ang[k]), sn = sin(g->ang[k]);
+    double sx = g->sid * c, sy = g->sid * sn;
+    double x0 = g->cx - 0.5 * g->nx * g->vx + ix * g->vx, y0 = g->cy - 0.5 * g->ny * g->vy + iy * g->vy;
+    *dmin = INFINITY;
+    *dmax = -INFINITY;
+    for (int q = 0; q < 4; ++q) {
+        double px = x0 + ((q & 1) ? g->vx : 0.0), py = y0 + ((q & 2) ? g->vy : 0.0);
+        double dx = px - sx, dy = py - sy;
+        double depth = -(c * dx + sn * dy);
+        tu[q] = g->sdd * (-sn * dx + c * dy) / depth;
+        if (depth < *dmin) *dmin = depth;
+        if (depth > *dmax) *dmax = depth;
+    }
+    tt_sort4(tu);
+}
+
+/* Axial breakpoints (mm on the detector v axis, sorted) of voxel layer iz. */
+static void tt_axial(const og_t *g, int iz, double dmin, double dmax, double tv[4])
+{
+    double zlo = g->cz - 0.5 * g->nz * g->vz + iz * g->vz, zhi = zlo + g->vz;
+    tv[0] = g->sdd * zlo / dmin;
+    tv[1] = g->sdd * zlo / dmax;
+    tv[2] = g->sdd * zhi / dmin;
+    tv[3] = g->sdd * zhi / dmax;
+    tt_sort4(tv);
+}
+
+/* L_i of every ray of view k, [iv][iu]. */
+static void tt_amplitudes(const og_t *g, int k, double *L)
+{
+    for (int iv = 0; iv < g->nv; ++iv)
+        for (int iu = 0; iu < g->nu; ++iu) {
+            double s[3], q[3];
+            og_ray(g, k, iv, iu, s, q);
+            double d[3] = { q[0] - s[0], q[1] - s[1], q[2] - s[2] };
+            double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double l = INFINITY;
+            double vox[3] = { g->vx, g->vy, g->vz };
+            for (int a = 0; a < 3; ++a)
+                if (d[a] != 0.0) {
+                    double la = vox[a] * n / fabs(d[a]);
+                    if (la < l) l = la;
+                }
+            L[(int64_t)iv * g->nu + iu] = l;
+        }
+}
+
+/* Detector index range [*a, *b] (clamped) whose pixels meet the open interval
+ * (t0, t3) of a detector axis with n pixels of pitch p and offset off. */
+static void tt_range(double t0, double t3, int n, double p, double off, int *a, int *b)
+{
+    double h = 0.5 * (double)(n - 1);
+    int lo = (int)ceil((t0 - off) / p + h - 0.5), hi = (int)floor((t3 - off) / p + h + 0.5);
+    *a = lo < 0 ? 0 : lo;
+    *b = hi > n - 1 ? n - 1 : hi;
+}
+
+static double tt_pixel_mean(const double t[4], int i, int n, double p, double off)
+{
+    double c = ((double)i - 0.5 * (double)(n - 1)) * p + off;
+    return (tt_cum(t, c + 0.5 * p) - tt_cum(t, c - 0.5 * p)) / p;
+}
+
+/* b = A_TT x.  Parallel over views; within a view voxels are visited in index
+ * order, so the sums are deterministic. */
+void oracle_tt_project(const int32_t *dims, const double *par, const double *angles, const double *x, double *b)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t per_view = (int64_t)g.nv * g.nu;
+    memset(b, 0, sizeof(double) * (size_t)(per_view * g.nviews));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int k = 0; k < g.nviews; ++k) {
+        double *bk = b + (int64_t)k * per_view;
+        double *L = (double *)malloc(sizeof(double) * (size_t)per_view);
+        tt_amplitudes(&g, k, L);
+        for (int iy = 0; iy < g.ny; ++iy)
+            for (int ix = 0; ix < g.nx; ++ix) {
+                double tu[4], dmin, dmax;
+                tt_transaxial(&g, k, ix, iy, tu, &dmin, &dmax);
+                int ua, ub;
+                tt_range(tu[0], tu[3], g.nu, g.du, g.off_u, &ua, &ub);
+                for (int iz = 0; iz < g.nz; ++iz) {
+                    double xv = x[((int64_t)iz * g.ny + iy) * g.nx + ix];
+                    if (xv == 0.0) continue;
+                    double tv[4];
+                    tt_axial(&g, iz, dmin, dmax, tv);
+                    int va, vb;
+                    tt_range(tv[0], tv[3], g.nv, g.dv, g.off_v, &va, &vb);
+                    for (int iu = ua; iu <= ub; ++iu) {
+                        double fu = tt_pixel_mean(tu, iu, g.nu, g.du, g.off_u);
+                        if (fu == 0.0) continue;
+                        for (int iv = va; iv <= vb; ++iv) {
+                            double fv = tt_pixel_mean(tv, iv, g.nv, g.dv, g.off_v);
+                            int64_t i = (int64_t)iv * g.nu + iu;
+                            bk[i] += L[i] * fu * fv * xv;
+                        }
+                    }
+                }
+            }
+        free(L);
+    }
+}
+
+/* r = A_TT^T y (square = 0), or r_j = sum_i a_ij^2 (square = 1, y unused).
+ * Each voxel gathers over its footprint in every view. */
+static void og_tt_gather(const int32_t *dims, const double *par, const double *angles, const double *y, double *r,
+                         int square)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t per_view = (int64_t)g.nv * g.nu;
+    int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    memset(r, 0, sizeof(double) * (size_t)nvox);
+    double *L = (double *)malloc(sizeof(double) * (size_t)(per_view * g.nviews));
+    for (int k = 0; k < g.nviews; ++k) tt_amplitudes(&g, k, L + (int64_t)k * per_view);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int iy = 0; iy < g.ny; ++iy)
+        for (int ix = 0; ix < g.nx; ++ix)
+            for (int k = 0; k < g.nviews; ++k) {
+                const double *yk = square ? y : y + (int64_t)k * per_view, *Lk = L + (int64_t)k * per_view;
+                double tu[4], dmin, dmax;
+                tt_transaxial(&g, k, ix, iy, tu, &dmin, &dmax);
+                int ua, ub;
+                tt_range(tu[0], tu[3], g.nu, g.du, g.off_u, &ua, &ub);
+                for (int iz = 0; iz < g.nz; ++iz) {
+                    double tv[4];
+                    tt_axial(&g, iz, dmin, dmax, tv);
+                    int va, vb;
+                    tt_range(tv[0], tv[3], g.nv, g.dv, g.off_v, &va, &vb);
+                    double acc = 0.0;
+                    for (int iu = ua; iu <= ub; ++iu) {
+                        double fu = tt_pixel_mean(tu, iu, g.nu, g.du, g.off_u);
+                        if (fu == 0.0) continue;
+                        for (int iv = va; iv <= vb; ++iv) {
+                            int64_t i = (int64_t)iv * g.nu + iu;
+                            double a = Lk[i] * fu * tt_pixel_mean(tv, iv, g.nv, g.dv, g.off_v);
+                            acc += square ? a * a : a * yk[i];
+                        }
+                    }
+                    r[((int64_t)iz * g.ny + iy) * g.nx + ix] += acc;
+                }
+            }
+    free(L);
+}
+
+void oracle_tt_backproject(const int32_t *dims, const double *par, const double *angles, const double *y, double *r)
+{
+    og_tt_gather(dims, par, angles, y, r, 0);
+}
+
+/* diag(A_TT^T A_TT)_j = sum_i a_ij^2. */
+void oracle_tt_diag_normal(const int32_t *dims, const double *par, const double *angles, double *out)
+{
+    og_tt_gather(dims, par, angles, NULL, out, 1);
 }
 
 int oracle_num_threads(void)

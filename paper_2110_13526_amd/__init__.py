@@ -60,14 +60,18 @@ class Geometry:
 
     Lengths in mm; view angles t_k = angle0 + k * arc / n_views unless
     ``angles`` is given (radians).  See include/kct.h for the convention.
+    ``projector`` is "siddon" (exact intersection lengths, the default) or
+    "tt" (separable trapezoid footprints, Section 3).
     """
+
+    PROJECTORS = {"siddon": _lib.PROJECTOR_SIDDON, "tt": _lib.PROJECTOR_TT}
 
     FIELDS = ("nx", "ny", "nz", "vx", "vy", "vz", "n_views", "nu", "nv", "du", "dv", "sid", "sdd", "cx", "cy",
               "cz", "off_u", "off_v", "angle0", "arc")
 
     def __init__(self, nx, ny, nz, vx, vy, vz, n_views, nu, nv, du, dv, sid=500.0, sdd=1000.0, cx=0.0, cy=0.0,
                  cz=0.0, off_u=0.0, off_v=0.0, angle0=0.0, arc=2.0 * math.pi,
-                 angles: Optional[Sequence[float]] = None, device=None):
+                 angles: Optional[Sequence[float]] = None, device=None, projector: str = "siddon"):
         torch = _torch()
         L = _lib.load()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -93,13 +97,23 @@ class Geometry:
         with torch.cuda.device(self.device):
             _lib.check(L.kct_geometry_create(ctypes.byref(vol), ctypes.byref(cone), ctypes.byref(h)))
         self._h = h
+        self.projector = "siddon"
+        if projector != "siddon":
+            self.set_projector(projector)
+
+    def set_projector(self, projector: str):
+        """Switch the projector model of every later call with this geometry."""
+        if projector not in self.PROJECTORS:
+            raise ValueError(f"projector must be one of {sorted(self.PROJECTORS)}")
+        _lib.check(_lib.load().kct_geometry_set_projector(self.handle, self.PROJECTORS[projector]))
+        self.projector = projector
 
     @classmethod
-    def from_desc(cls, d, device=None):
+    def from_desc(cls, d, device=None, projector: str = "siddon"):
         """Build from any object with the geometry attributes (e.g. kct_inputs.ConeGeometry)."""
         kw = {f: getattr(d, f) for f in cls.FIELDS}
         ang = getattr(d, "explicit_angles", None)
-        return cls(**kw, angles=ang, device=device)
+        return cls(**kw, angles=ang, device=device, projector=projector)
 
     @property
     def handle(self):

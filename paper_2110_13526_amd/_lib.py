@@ -22,8 +22,10 @@ EXPORTS = (
     "kct_geometry_create", "kct_geometry_destroy", "kct_geometry_dims", "kct_project_workspace_size",
     "kct_project", "kct_backproject", "kct_solver_workspace_size", "kct_cgls_solve", "kct_lsqr_solve",
     "kct_diag_normal", "kct_batch_create", "kct_batch_destroy", "kct_batch_workspace_size", "kct_batch_tune",
-    "kct_batch_cgls_solve", "kct_last_error",
+    "kct_batch_cgls_solve", "kct_geometry_set_projector", "kct_last_error",
 )
+
+PROJECTOR_SIDDON, PROJECTOR_TT = 0, 1
 
 
 class VolumeDesc(ctypes.Structure):
@@ -92,6 +94,8 @@ def load():
         f.restype = st
     L.kct_diag_normal.argtypes = [vp, vp, vp]
     L.kct_diag_normal.restype = st
+    L.kct_geometry_set_projector.argtypes = [vp, ctypes.c_int32]
+    L.kct_geometry_set_projector.restype = st
     L.kct_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(vp)]
     L.kct_batch_create.restype = st
     L.kct_batch_destroy.argtypes = [vp]

@@ -11,6 +11,7 @@
 #include <type_traits>
 
 #include "kct_batch.h"
+#include "kct_epilogue.h"
 #include "kct_gather.h"
 #include "kct_internal.h"
 #include "kct_weights.h"
@@ -140,27 +141,10 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
             if (j >= nzb) continue;
             const int iz = iz0 + j;
             const size_t vox = ((size_t)iz * g.ny + iy) * g.nx + ix;
-            A o;
-            if (EPI == BWD_LSQR0) o = (A)sc->bwd_c1 * acc[j];
-            else if (EPI == BWD_LSQR) o = (A)sc->bwd_c1 * acc[j] - (A)sc->bwd_c2 * to_acc(out[vox]);
-            else if (EPI == BWD_NORM) o = (A)sc->bwd_scale * acc[j];
-            else if (EPI == BWD_TIK) o = (A)sc->bwd_scale * acc[j] - (A)sc->tik_r * (A)aux[vox];
-            else if (EPI == BWD_JACOBI) o = (A)aux[vox] * acc[j];
-            else if (EPI == BWD_DIAG_INV) o = acc[j] > 0 ? (A)1 / acc[j] : (A)0;
-            else o = acc[j];
-            const T st = store_as<T>(o);
-            out[vox] = st;
-            if (EPI == BWD_LSQR0 || EPI == BWD_LSQR) out_z[((size_t)iy * g.nx + ix) * g.nz + iz] = st;
-            if (EPI == BWD_JACOBI) {  // |M A^T e|^2 with M^2 = aux: the preconditioned residual norm
-                const double a = (double)acc[j];
-                sq += (double)aux[vox] * a * a;
-            } else {
-                const double od = (double)to_acc(st);
-                sq += od * od;
-            }
+            sq += bwd_store<T, EPI, A>(out, out_z, sc, aux, vox, ((size_t)iy * g.nx + ix) * g.nz + iz, acc[j]);
         }
     }
-    if (EPI != BWD_PLAIN && EPI != BWD_DIAG && EPI != BWD_DIAG_INV) {
+    if (bwd_has_partials<EPI>()) {
         const double bs = bwd_block_sum(sq);
         if (threadIdx.x == 0) partials[w] = bs;
     }
@@ -232,6 +216,7 @@ template <typename T>
 hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
                            double *partials, const int *skip, hipStream_t st, const float *aux)
 {
+    if (g.projector == KCT_PROJECTOR_TT) return launch_backward_tt<T>(g, proj, out, out_z, epi, sc, partials, skip, st, aux);
     int nbx, nby, nbz;
     bwd_grid(g, nbx, nby, nbz);
     const dim3 grid((unsigned)(nbx * nby * nbz));

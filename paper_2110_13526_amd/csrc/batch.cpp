@@ -147,9 +147,10 @@ kct_status kct_batch_create(const kct_geometry *geoms, int32_t count, kct_batch 
     b->device = dev;
     for (int i = 0; i < count; ++i) {
         const Geometry *g = reinterpret_cast<const Geometry *>(geoms[i]);
-        if (!g || g->device != dev) {
+        if (!g || g->device != dev || g->dev.projector != KCT_PROJECTOR_SIDDON) {
             delete b;
-            return fail(fn, "geometry " + std::to_string(i) + " is NULL or on another device", KCT_ERR_INVALID_ARG);
+            return fail(fn, "geometry " + std::to_string(i) + " is NULL, on another device or not a Siddon geometry",
+                        KCT_ERR_INVALID_ARG);
         }
         b->geoms.push_back(g);
         b->fwd_r.push_back(2);

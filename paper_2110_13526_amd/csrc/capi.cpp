@@ -36,7 +36,11 @@ int64_t nrays(const Geometry *g) { return (int64_t)g->dev.nviews * g->dev.nv * g
 
 int64_t num_partials(const Geometry *g)
 {
-    int64_t a = forward_num_blocks(g->dev), b = backward_num_blocks(g->dev), c = stream_num_blocks();
+    // the largest forward grid of every projector and variant (the workspace may
+    // be sized before the projector is chosen)
+    int64_t a = forward_num_blocks_r(g->dev, 1), b = backward_num_blocks(g->dev), c = stream_num_blocks();
+    const int64_t t = tt_forward_num_blocks(g->dev);
+    if (t > a) a = t;
     int64_t m = a > b ? a : b;
     return m > c ? m : c;
 }
@@ -453,6 +457,20 @@ void kct_geometry_destroy(kct_geometry h)
     Geometry *g = reinterpret_cast<Geometry *>(h);
     if (g->d_tables) (void)hipFree(g->d_tables);
     delete g;
+}
+
+kct_status kct_geometry_set_projector(kct_geometry h, int32_t projector)
+{
+    if (!h) {
+        set_error("kct_geometry_set_projector: geometry is NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    if (projector != KCT_PROJECTOR_SIDDON && projector != KCT_PROJECTOR_TT) {
+        set_error("kct_geometry_set_projector: unknown projector");
+        return KCT_ERR_INVALID_ARG;
+    }
+    reinterpret_cast<Geometry *>(h)->dev.projector = projector;
+    return KCT_OK;
 }
 
 kct_status kct_geometry_dims(kct_geometry h, int64_t *n_vox, int64_t *n_rays)

@@ -149,6 +149,8 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
     d.inv_du = (float)(1.0 / cone.du);
     d.inv_dv = (float)(1.0 / cone.dv);
     d.cu = 0.5f * (float)(nu - 1);
+    d.projector = KCT_PROJECTOR_SIDDON;
+    d.sid = (float)cone.sid;
     d.cv = 0.5f * (float)(nv - 1);
     d.cols = nullptr;
     d.rows = nullptr;

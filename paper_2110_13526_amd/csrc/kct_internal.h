@@ -63,6 +63,8 @@ struct GeoDev {
     float sdd, du, dv, off_u, off_v;
     float inv_du, inv_dv;
     float cu, cv;            // (nu - 1)/2, (nv - 1)/2
+    int projector;           // KCT_PROJECTOR_SIDDON or KCT_PROJECTOR_TT (host-side dispatch)
+    float sid;               // source to rotation axis [mm]
     const ColParam *cols;    // [nviews][nu]
     const RowParam *rows;    // [nv]
     const ViewParam *views;  // [nviews]
@@ -183,6 +185,15 @@ hipError_t launch_cgls_e(T *e, const T *p, const Scalars *sc, int64_t n, double 
 // LSQR: w = w_vcoef v (init) or x += x_coef w; w = w_vcoef v - w_coef w
 template <typename T>
 hipError_t launch_lsqr_xw(float *x, T *w, const T *v, const Scalars *sc, int init, int64_t n, hipStream_t st);
+// the TT footprint pair (tt.hip); launch_forward / launch_backward dispatch to
+// them for geometries whose projector is KCT_PROJECTOR_TT
+template <typename TV, typename TP>
+hipError_t launch_forward_tt(const GeoDev &g, const TV *vol, const TV *vol_z, TP *out, const TP *aux, int epi,
+                             const Scalars *sc, double *partials, const int *skip, hipStream_t st);
+template <typename T>
+hipError_t launch_backward_tt(const GeoDev &g, const T *proj, T *out, T *out_z, int epi, const Scalars *sc,
+                              double *partials, const int *skip, hipStream_t st, const float *aux);
+int64_t tt_forward_num_blocks(const GeoDev &g);
 // forward with an explicit rows-per-lane variant (1 or 2), plain epilogue
 hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_z, float *out, int rows_per_lane,
                             hipStream_t st);

@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "kct_batch.h"
+#include "kct_epilogue.h"
 #include "kct_internal.h"
 #include "kct_ray.h"
 #include "kct_weights.h"
@@ -129,15 +130,7 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
         if (!ok[r]) continue;
         const int iv = band * FWD_ROWS + lane + 64 * r;
         const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
-        A o;
-        if (EPI == FWD_BMINUS) o = to_acc(aux[ray]) - p[r];
-        else if (EPI == FWD_LSQR) o = (A)sc->fwd_c1 * p[r] - (A)sc->fwd_c2 * to_acc(out[ray]);
-        else if (EPI == FWD_NORM) o = (A)sc->fwd_scale * p[r];
-        else o = p[r];
-        const TP st = store_as<TP>(o);
-        out[ray] = st;
-        const double od = (double)to_acc(st);
-        sq += od * od;
+        sq += fwd_store<TP, EPI, A>(out, aux, sc, ray, p[r]);
     }
     if (EPI != FWD_PLAIN) {
         const double bs = block_sum_256(sq);
@@ -163,13 +156,17 @@ __global__ __launch_bounds__(256) void k_forward_r(GeoDev g, const TV *__restric
     forward_block<TV, TP, EPI, R>(g, blockIdx.x, vol, vol_z, out, nullptr, nullptr, nullptr);
 }
 
-int64_t forward_num_blocks(const GeoDev &g) { return fwd_grid(g, FWD_R).nblocks; }
+int64_t forward_num_blocks(const GeoDev &g)
+{
+    return g.projector == KCT_PROJECTOR_TT ? tt_forward_num_blocks(g) : fwd_grid(g, FWD_R).nblocks;
+}
 int64_t forward_num_blocks_r(const GeoDev &g, int rows_per_lane) { return fwd_grid(g, rows_per_lane).nblocks; }
 
 template <typename TV, typename TP>
 hipError_t launch_forward(const GeoDev &g, const TV *vol, const TV *vol_z, TP *out, const TP *aux, int epi,
                           const Scalars *sc, double *partials, const int *skip, hipStream_t st)
 {
+    if (g.projector == KCT_PROJECTOR_TT) return launch_forward_tt<TV, TP>(g, vol, vol_z, out, aux, epi, sc, partials, skip, st);
     dim3 grid((unsigned)fwd_grid(g, FWD_R).nblocks);
     dim3 block(256);
     if constexpr (std::is_same<TV, double>::value) {  // double storage: plain projection only

@@ -1,0 +1,184 @@
+"""The separable trapezoid-footprint (TT) projector pair on the GPU against the
+FP64 oracle, through the C ABI (Section 3's projector model; the projector of
+the experiments in Section 4).
+
+Tolerances as for the Siddon pair: relative L2 error 1e-5 for single-precision
+projections and backprojections, 1e-4 for FP32 solver iterates after K
+iterations; double-precision projections agree with the oracle to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import kct_inputs as ki
+import oracle
+from tests.gpu_util import dev, rel, say, to_dev, to_np, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+SMALL = {
+    "t16": ki.t16("base"),
+    "t16_offcenter": ki.t16("offcenter"),
+    "t16_aniso": ki.t16("aniso"),
+    "t16_odd": ki.t16("odd"),
+    "c1": ki.config("c1"),
+    # detector not a multiple of the 64-row / 4-column ray tile, volume not a
+    # multiple of the 16^3 brick, views through 45 degrees
+    "ragged": ki.ConeGeometry(37, 29, 23, 0.9, 1.1, 1.3, n_views=7, nu=77, nv=19, du=1.3, dv=1.7, cx=1.2,
+                              cy=-0.7, cz=2.1, off_u=0.9, off_v=-1.4, angle0=np.pi / 4),
+    "one_voxel": ki.ConeGeometry(1, 1, 1, 3.0, 3.0, 3.0, n_views=5, nu=9, nv=7, du=1.0, dv=1.0),
+}
+
+
+def tt_geometry(desc):
+    import paper_2110_13526_amd as kct
+    return kct.Geometry.from_desc(desc, device=dev(), projector="tt")
+
+
+@pytest.fixture(scope="module", params=sorted(SMALL))
+def case(request):
+    name = request.param
+    g = SMALL[name]
+    say(f"[tt] case {name}: vol {g.vol_shape} proj {g.proj_shape}")
+    return name, g, tt_geometry(g)
+
+
+def test_forward_matches_oracle(case):
+    name, g, G = case
+    import paper_2110_13526_amd as kct
+    for x in (ki.random_volume(g, 1), ki.phantom(g, 8, 2, dtype=np.float64)):
+        x32 = x.astype(np.float32)
+        b = to_np(kct.project(G, to_dev(x32)))
+        ref = oracle.tt_project(g, x32.astype(np.float64))
+        err = rel(b, ref)
+        say(f"  forward rel {err:.3e}")
+        assert err < TOL, (name, err)
+
+
+def test_backward_matches_oracle(case):
+    name, g, G = case
+    import paper_2110_13526_amd as kct
+    y = (1.0 + 0.5 * ki.random_projections(g, 3)).astype(np.float32)
+    r = to_np(kct.backproject(G, to_dev(y)))
+    ref = oracle.tt_backproject(g, y.astype(np.float64))
+    err = rel(r, ref)
+    say(f"  backward rel {err:.3e}")
+    assert err < TOL, (name, err)
+
+
+def test_layouts_and_determinism(case):
+    name, g, G = case
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    x = to_dev(ki.phantom(g, 6, 7))
+    b1 = kct.project(G, x)
+    b2 = kct.project(G, x, transposed_copy=False)
+    b3 = kct.project(G, x)
+    assert torch.equal(b1, b2) and torch.equal(b1, b3)
+    y = to_dev(ki.random_projections(g, 8))
+    assert torch.equal(kct.backproject(G, y), kct.backproject(G, y))
+
+
+def test_double_precision_matches_oracle(case):
+    """FP64 storage and accumulation: the pair reproduces the oracle to rounding."""
+    name, g, G = case
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    x = ki.random_volume(g, 5).astype(np.float64)
+    y = ki.random_projections(g, 6).astype(np.float64)
+    b = to_np(kct.project(G, torch.from_numpy(x).to(dev())))
+    r = to_np(kct.backproject(G, torch.from_numpy(y).to(dev())))
+    eb, er = rel(b, oracle.tt_project(g, x)), rel(r, oracle.tt_backproject(g, y))
+    say(f"  f64 forward {eb:.3e} backward {er:.3e}")
+    # the weights are formed in single precision on both sides of the pair
+    # (bitwise equal in the kernels), the oracle forms them in double
+    assert eb < TOL and er < TOL
+    lhs = float(np.dot(b.ravel(), y.ravel()))
+    rhs = float(np.dot(x.ravel(), r.ravel()))
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(b) * np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("name", ["t16", "t16_odd", "t16_offcenter", "ragged"])
+def test_weights_bitwise_identical(name):
+    """A column of A (forward of e_j) and a row of A (backprojection of e_i) hold the same weight bits."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    g = SMALL[name]
+    G = tt_geometry(g)
+    rng = np.random.default_rng(12)
+    checked = 0
+    for j in rng.choice(g.n_vox, 8, replace=False):
+        x = torch.zeros(g.n_vox, dtype=torch.float32, device=dev())
+        x[j] = 1.0
+        col = kct.project(G, x.view(g.vol_shape)).view(-1)
+        nz = torch.nonzero(col).view(-1).cpu().numpy()
+        for i in rng.choice(nz, min(6, nz.size), replace=False) if nz.size else []:
+            y = torch.zeros(g.n_rays, dtype=torch.float32, device=dev())
+            y[i] = 1.0
+            row = kct.backproject(G, y.view(g.proj_shape)).view(-1)
+            assert row[j].view(torch.int32).item() == col[i].view(torch.int32).item()
+            checked += 1
+    assert checked > 0
+
+
+@pytest.mark.parametrize("name", ["t16_offcenter", "ragged", "c1"])
+def test_diag_normal(name):
+    import paper_2110_13526_amd as kct
+    g = SMALL[name]
+    G = tt_geometry(g)
+    err = rel(to_np(kct.diag_normal(G)), oracle.tt_diag_normal(g))
+    say(f"[tt] diag {name}: rel {err:.3e}")
+    assert err < TOL
+
+
+def test_projector_switch_and_reject():
+    """Switching the model changes the operator; unknown models are rejected."""
+    import paper_2110_13526_amd as kct
+    g = SMALL["t16"]
+    G = tt_geometry(g)
+    x = to_dev(ki.phantom(g, 6, 3))
+    bt = to_np(kct.project(G, x))
+    G.set_projector("siddon")
+    bs = to_np(kct.project(G, x))
+    assert rel(bs, oracle.project(g, to_np(x))) < TOL
+    assert rel(bt, bs) > 1e-3
+    with pytest.raises(ValueError):
+        G.set_projector("joseph")
+    from paper_2110_13526_amd import _lib
+    assert _lib.load().kct_geometry_set_projector(G.handle, 7) == _lib.KCT_ERR_INVALID_ARG
+    with pytest.raises(Exception):
+        kct.Batch([tt_geometry(g)])
+
+
+@pytest.fixture(scope="module")
+def c1_tt():
+    g = ki.config("c1")
+    x_true = ki.phantom(g, ki.N_ELLIPSOIDS["c1"], ki.SEEDS["c1"])
+    b = oracle.tt_project(g, x_true.astype(np.float64))
+    b = ki.gaussian_noise(b, 0.005, ki.SEEDS["c1"] + 1_000_000).astype(np.float32)
+    return g, tt_geometry(g), b
+
+
+@pytest.mark.parametrize("solver", ["cgls", "lsqr"])
+def test_solvers_match_oracle(c1_tt, solver):
+    import paper_2110_13526_amd as kct
+    g, G, b = c1_tt
+    K = 10
+    ref = getattr(oracle, solver)(g, b.astype(np.float64), K, projector="tt")
+    x, info = getattr(kct, solver)(G, to_dev(b), K, history=True)
+    err = rel(to_np(x), ref.x)
+    herr = float(np.max(np.abs(to_np(info.history) - ref.history) / ref.history))
+    say(f"[tt] {solver}: x rel {err:.3e}, history {herr:.3e}")
+    assert err < 1e-4 and herr < 1e-4
+
+
+def test_cgls_tikhonov_and_recompute(c1_tt):
+    import paper_2110_13526_amd as kct
+    g, G, b = c1_tt
+    ref = oracle.cgls(g, b.astype(np.float64), 8, tikhonov=20.0, projector="tt")
+    x, _ = kct.cgls(G, to_dev(b), 8, tikhonov=20.0)
+    assert rel(to_np(x), ref.x) < 1e-4
+    ref = oracle.cgls(g, b.astype(np.float64), 8, recompute_every=3, projector="tt")
+    x, _ = kct.cgls(G, to_dev(b), 8, recompute_every=3)
+    assert rel(to_np(x), ref.x) < 1e-4

@@ -400,3 +400,108 @@ def test_tikhonov_cgls_with_initial_guess(small_problem):
     rhs = np.concatenate([b.ravel(), np.zeros(A.shape[1])])
     ref = spla.lsqr(S, rhs, atol=0.0, btol=0.0, conlim=0.0, iter_lim=K, x0=x0)[0]
     assert rel(oracle.cgls(g, b, K, x0=x0, tikhonov=lam).x.ravel(), ref) < 1e-8
+
+
+# ------------------------------------------------------ TT footprint projector
+
+def test_tt_uniform_volume_is_exact_chord():
+    """Neighbouring voxels' trapezoids sum to one, so for a uniform volume every
+    ray that enters and leaves through the two faces normal to its dominant axis
+    gets exactly its chord (the same value as the Siddon projector)."""
+    g = ki.t16("base").replace(n_views=2, explicit_angles=[0.0, np.pi / 2])
+    ones = np.ones(g.vol_shape)
+    bt = oracle.tt_project(g, ones)
+    bs = oracle.project(g, ones)
+    c = slice(20, 28)  # central rays: they cross the volume between the x (view 0) or y (view 1) faces
+    assert np.abs(bt[:, c, c] - bs[:, c, c]).max() < 1e-12 * bs[:, c, c].max()
+    # and they are the closed-form chords through the volume box
+    lo = np.array([g.cx - g.nx * g.vx / 2, g.cy - g.ny * g.vy / 2, g.cz - g.nz * g.vz / 2])
+    hi = lo + np.array([g.nx * g.vx, g.ny * g.vy, g.nz * g.vz])
+    chord = bf.box_chord(g, lo, hi)
+    assert np.abs(bt[:, c, c] - chord[:, c, c]).max() < 1e-12 * chord[:, c, c].max()
+
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "aniso", "odd"])
+def test_tt_support_contains_every_ray_through_the_voxel(variant):
+    """The TT footprint of a voxel is its exact shadow (widened by the linear
+    ramps only inside it): every ray that crosses the voxel (positive Siddon
+    weight) has a positive TT weight, and no ray far outside the shadow has one."""
+    g = ki.t16(variant)
+    rng = np.random.default_rng(11)
+    for j in rng.choice(g.n_vox, 12, replace=False):
+        e = np.zeros(g.n_vox)
+        e[j] = 1.0
+        bs = oracle.project(g, e.reshape(g.vol_shape))
+        bt = oracle.tt_project(g, e.reshape(g.vol_shape))
+        assert np.all(bt[bs > 1e-9] > 0)
+        assert np.all(bt >= 0)
+        # TT's support is at most one pixel wider than the shadow of the rays
+        ks, vs, us = np.nonzero(bt > 0)
+        ks2, vs2, us2 = np.nonzero(bs > 0)
+        for k in set(ks2.tolist()):
+            assert us[ks == k].min() >= us2[ks2 == k].min() - 1 and us[ks == k].max() <= us2[ks2 == k].max() + 1
+            assert vs[ks == k].min() >= vs2[ks2 == k].min() - 1 and vs[ks == k].max() <= vs2[ks2 == k].max() + 1
+
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "odd"])
+def test_tt_adjoint(variant):
+    """The scatter (forward) and the gather (backward) of the TT oracle are
+    each other's transpose."""
+    g = ki.t16(variant)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(g.vol_shape)
+    y = rng.standard_normal(g.proj_shape)
+    lhs = float((oracle.tt_project(g, x) * y).sum())
+    rhs = float((x * oracle.tt_backproject(g, y)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_tt_pixel_means_by_quadrature():
+    """F_u F_v of single voxels against a midpoint-rule quadrature of the two
+    trapezoids over each pixel (2000 x 2000 samples per pixel would be
+    needless; the trapezoids are separable, so 4000 samples per axis)."""
+    g = ki.ConeGeometry(4, 4, 4, 2.0, 2.0, 2.0, 3, 14, 12, 1.3, 1.1, sid=60.0, sdd=120.0, cx=0.4, cy=-0.3, cz=0.2)
+    src_all, Q = bf.rays(g)
+    for j in [0, 21, 42, 63]:
+        iz, iy, ix = np.unravel_index(j, g.vol_shape)
+        e = np.zeros(g.vol_shape)
+        e[iz, iy, ix] = 1.0
+        bt = oracle.tt_project(g, e)
+        lo = np.array([g.cx - g.nx * g.vx / 2 + ix * g.vx, g.cy - g.ny * g.vy / 2 + iy * g.vy,
+                       g.cz - g.nz * g.vz / 2 + iz * g.vz])
+        for k in range(g.n_views):
+            th = g.angles()[k]
+            c, s = np.cos(th), np.sin(th)
+            src = np.array([g.sid * c, g.sid * s, 0.0])
+            corners = [(lo[0] + a * g.vx, lo[1] + b * g.vy) for a in (0, 1) for b in (0, 1)]
+            dep = [-(c * (px - src[0]) + s * (py - src[1])) for px, py in corners]
+            tu = sorted(g.sdd * (-s * (px - src[0]) + c * (py - src[1])) / d for (px, py), d in zip(corners, dep))
+            tv = sorted(g.sdd * z / d for z in (lo[2], lo[2] + g.vz) for d in (min(dep), max(dep)))
+
+            def trap(t, u):
+                up = np.clip((u - t[0]) / max(t[1] - t[0], 1e-300), 0, 1)
+                dn = np.clip((t[3] - u) / max(t[3] - t[2], 1e-300), 0, 1)
+                return np.minimum(up, dn)
+
+            for iv in range(g.nv):
+                for iu in range(g.nu):
+                    uc = (iu - (g.nu - 1) / 2) * g.du + g.off_u
+                    vc = (iv - (g.nv - 1) / 2) * g.dv + g.off_v
+                    us = uc + ((np.arange(4000) + 0.5) / 4000 - 0.5) * g.du
+                    vs = vc + ((np.arange(4000) + 0.5) / 4000 - 0.5) * g.dv
+                    fu, fv = trap(tu, us).mean(), trap(tv, vs).mean()
+                    d = Q[k, iv, iu] - src_all[k]
+                    L = min(vox / abs(di) for vox, di in zip((g.vx, g.vy, g.vz), d / np.linalg.norm(d)) if di != 0)
+                    assert abs(bt[k, iv, iu] - L * fu * fv) <= 1e-6 * L, (j, k, iv, iu)
+
+
+def test_tt_approaches_siddon_with_resolution():
+    """Both projectors approximate the same line integrals; on a fixed smooth
+    object their difference shrinks as the voxels get finer."""
+    diffs = []
+    for n in (16, 32, 64):
+        g = ki.ConeGeometry(n, n, n, 32.0 / n, 32.0 / n, 32.0 / n, 8, 64, 64, 1.0, 1.0)
+        x = ki.voxelize(g, ki.draw_ellipsoids(g, 6, 7))
+        bt, bs = oracle.tt_project(g, x), oracle.project(g, x)
+        diffs.append(rel(bt, bs))
+    assert diffs[0] > diffs[1] > diffs[2] and diffs[2] < 0.025, diffs
