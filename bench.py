@@ -82,6 +82,7 @@ def main():
     ap.add_argument("--cpu-views", type=int, default=96, help="views in the CPU-oracle sample")
     ap.add_argument("--nnz-views", type=int, default=90, help="views sampled to count nonzeros")
     ap.add_argument("--no-precision", action="store_true", help="skip the BF16 / FP16 comparison solves")
+    ap.add_argument("--no-tt", action="store_true", help="skip the timing of the TT footprint projector pair")
     ap.add_argument("--kernels-only", action="store_true",
                     help="profiling pass: one forward, one backward and one 1 GiB device copy (the "
                          "calibration of the HBM byte counters), nothing timed")
@@ -188,6 +189,17 @@ def main():
                 "forward_GBs": round(fwd_bytes / t_fwd / 1e9, 1), "backward_GBs": round(bwd_bytes / t_bwd / 1e9, 1),
                 "nnz_per_application": float(f"{nnz:.4g}")}
 
+    # --- the separable trapezoid-footprint pair on the same workload (secondary)
+    tt = None
+    if not args.no_tt:
+        G.set_projector("tt")
+        t_fwd_tt = timed(lambda: kct.project(G, xin, out=pbuf, workspace=pws), 2)
+        t_bwd_tt = timed(lambda: kct.backproject(G, b, out=vbuf), 2)
+        G.set_projector("siddon")
+        tt = {"forward_ms": round(t_fwd_tt * 1e3, 3), "backward_ms": round(t_bwd_tt * 1e3, 3),
+              "pair_per_s": round(1.0 / (t_fwd_tt + t_bwd_tt), 4)}
+        log(f"[bench] TT pair: forward {t_fwd_tt * 1e3:.2f} ms, backward {t_bwd_tt * 1e3:.2f} ms per launch")
+
     cpu = None
     if not args.no_cpu:
         xs = x_true.astype(np.float64)
@@ -245,6 +257,7 @@ def main():
                    "rel_error_vs_x_true": round(rec_err, 6), "parallelism": "single GPU"},
         "roofline": roofline,
         "precision": precision,
+        "tt_projector": tt,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
