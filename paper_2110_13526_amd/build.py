@@ -5,7 +5,10 @@
 Compiles every source under ``csrc/`` with hipcc as HIP (device code for
 gfx950 only), with floating-point contraction off (the weight function must
 round identically in the forward and the backward kernel) and packed-FP32
-instructions disabled.
+instructions disabled.  The projector kernels (which form no NaN: every
+infinity they use is an explicit sentinel) are compiled without IEEE-mode
+min/max, so fminf/fmaxf need no operand canonicalisation; the solver kernels,
+which test for non-finite values, keep the default.
 """
 from __future__ import annotations
 
@@ -32,6 +35,15 @@ def flags():
     ]
 
 
+PROJECTOR_SOURCES = {"projector.hip", "backproject.hip", "tt.hip"}
+
+
+def source_flags(src):
+    if os.path.basename(src) in PROJECTOR_SOURCES:
+        return ["-fno-honor-nans", "-mno-amdgpu-ieee"]
+    return []
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile each source to an object in parallel, then link the shared library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -42,7 +54,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *flags(), "-x", "hip", "-c", src, "-o", obj]
+        cmd = [hipcc, *flags(), *source_flags(src), "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
