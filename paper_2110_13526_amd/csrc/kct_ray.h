@@ -13,10 +13,14 @@
 namespace kct {
 
 // z-walk state of one ray: current z-cell mz (-1 / nz stand for "below" /
-// "above" the volume), walking direction stz, index hb of the plane where the
-// walk leaves mz, and the crossings lz (entry into mz) and hzv (exit from mz).
+// "above" the volume), walking direction stz (and as a float, fstz), the
+// centred coordinate hbf of the plane where the walk leaves mz (an exact small
+// integer or half-integer, so stepping it by +-1 is exact), and the crossings lz
+// (entry into mz) and hzv (exit from mz; +inf once the walk has left the
+// volume's planes).
 struct ZWalk {
-    int mz, stz, hb;
+    int mz, stz;
+    float hbf, fstz;
     float lz, hzv, zeta_c, czr;
 };
 
@@ -29,10 +33,11 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
 {
     s.zeta_c = zeta_c;
     s.czr = czr;
+    s.hbf = 0.0f;
+    s.fstz = 0.0f;
     if (czr == 0.0f) {
         s.mz = parallel_cell(zeta_c, hz);
         s.stz = 0;
-        s.hb = 0;
         s.lz = -INFINITY;
         s.hzv = INFINITY;
         if (s.mz < 0 || s.mz >= nz) { s.mz = -1; s.lz = INFINITY; }
@@ -42,35 +47,47 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
     if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) {
         s.mz = -1;
         s.stz = 0;
-        s.hb = 0;
         s.lz = INFINITY;
         s.hzv = INFINITY;
         return;
     }
     s.stz = czr > 0.0f ? 1 : -1;
+    s.fstz = (float)s.stz;
     const int m = (int)floorf(zeta_c + t_start / czr + hz) - s.stz;
     s.mz = m < -1 ? -1 : (m > nz ? nz : m);
-    s.hb = s.stz > 0 ? s.mz + 1 : s.mz;
-    const int lb = s.hb - s.stz;
+    const int hb = s.stz > 0 ? s.mz + 1 : s.mz;
+    const int lb = hb - s.stz;
+    s.hbf = (float)hb - hz;
     s.lz = (lb >= 0 && lb <= nz) ? cross_at((float)lb - hz, zeta_c, czr) : -INFINITY;
-    s.hzv = (s.hb >= 0 && s.hb <= nz) ? cross_at((float)s.hb - hz, zeta_c, czr) : INFINITY;
+    s.hzv = (hb >= 0 && hb <= nz) ? cross_at(s.hbf, zeta_c, czr) : INFINITY;
 }
 
-// Add the ray's part inside the in-plane piece [t0, t1] (in-plane cell at
-// volume offset base) to acc, stepping through z-cells while the ray crosses
-// z-planes before t1.
-template <typename T>
-__host__ __device__ __forceinline__ void zwalk_piece(ZWalk &s, const T *__restrict__ vol, int base, int sz, int nz,
-                                                     float hz, float t0, float t1, acc_t<T> &acc)
+// Add fl(w) * x of the ray's current z-cell inside the piece [t0, t1] (the
+// column of the piece starts at col; element m of it at col[m * SZ]).
+template <typename T, int SZ>
+__host__ __device__ __forceinline__ void zwalk_eval(const ZWalk &s, const T *__restrict__ col, int sz, int nz,
+                                                    float t0, float t1, acc_t<T> &acc)
 {
-    for (int guard = nz + 2; guard > 0; --guard) {
-        const float w = fminf(t1, s.hzv) - fmaxf(t0, s.lz);
-        if (w > 0.0f && (unsigned)s.mz < (unsigned)nz) acc = fma_acc(w, to_acc(vol[base + s.mz * sz]), acc);
-        if (!(s.hzv < t1)) break;
+    const float w = fminf(t1, s.hzv) - fmaxf(t0, s.lz);
+    if (w > 0.0f && (unsigned)s.mz < (unsigned)nz) {
+        const unsigned off = SZ == 1 ? (unsigned)s.mz : (unsigned)s.mz * (unsigned)sz;
+        acc = fma_acc(w, to_acc(col[off]), acc);
+    }
+}
+
+// The rest of the ray's part inside the in-plane piece [t0, t1] (in-plane cell
+// whose z-column starts at col) after its current z-cell: one more z-cell per
+// z-plane crossed before t1 (usually none or one: z-slopes are small).
+template <typename T, int SZ>
+__host__ __device__ __forceinline__ void zwalk_steps(ZWalk &s, const T *__restrict__ col, int sz, int nz, float hz,
+                                                     float t0, float t1, acc_t<T> &acc)
+{
+    for (int guard = nz + 1; s.hzv < t1 && guard > 0; --guard) {
         s.lz = s.hzv;
         s.mz += s.stz;
-        s.hb += s.stz;
-        s.hzv = (s.hb >= 0 && s.hb <= nz) ? cross_at((float)s.hb - hz, s.zeta_c, s.czr) : INFINITY;
+        s.hbf += s.fstz;
+        s.hzv = fabsf(s.hbf) <= hz ? cross_at(s.hbf, s.zeta_c, s.czr) : INFINITY;
+        zwalk_eval<T, SZ>(s, col, sz, nz, t0, t1, acc);
     }
 }
 
@@ -91,8 +108,10 @@ __host__ __device__ __forceinline__ void zwalk_piece(ZWalk &s, const T *__restri
 // always the crossing at which the current in-plane cell was entered).
 // Volume addressing: element (zeta cell m, xi cell i, eta cell e) is at
 // vol[m * sz + i * sxi + e * seta].  With the z-fastest copy of the volume
-// (sz = 1), lanes that hold neighbouring rows read neighbouring addresses.
-template <typename T, int R>
+// (sz = 1, which SZ = 1 fixes at compile time), lanes that hold neighbouring
+// rows read neighbouring addresses.  The in-plane walk depends on the column
+// only: with uniform column parameters it runs on scalar branches.
+template <typename T, int R, int SZ = 0>
 __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, int sxi, int seta, int sz, int nxi,
                                                     int neta, int nz, float hxi, float heta, float hz, float eta_c,
                                                     float inv_a, float a, const float (&zeta_c)[R],
@@ -164,8 +183,53 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
     float t0 = t_start;
     for (int guard = nxi + neta + 4; t0 < t_end && guard > 0; --guard) {
         const float t1 = fminf(hx, he);
+        const T *col = vol + base;
+        // The current z-cell of every row first, with the R loads issued
+        // together (a lane without a contribution reads element 0 of the column,
+        // which exists, and keeps its sum), then the z-cells entered inside the
+        // piece: the same additions in the same order as zwalk_piece.
+        float w[R];
+        bool ok[R];
+        T v[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) zwalk_piece<T>(zs[r], vol, base, sz, nz, hz, t0, t1, acc[r]);
+        for (int r = 0; r < R; ++r) {
+            w[r] = fminf(t1, zs[r].hzv) - fmaxf(t0, zs[r].lz);
+            ok[r] = w[r] > 0.0f && (unsigned)zs[r].mz < (unsigned)nz;
+            const unsigned off = !ok[r] ? 0u : (SZ == 1 ? (unsigned)zs[r].mz : (unsigned)zs[r].mz * (unsigned)sz);
+            v[r] = col[off];
+        }
+        // the first z-plane crossed inside the piece, if any: every lane steps
+        // (kept only where the ray crosses) and the R loads again go out together
+        float w2[R];
+        bool ok2[R];
+        T v2[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            ZWalk &z = zs[r];
+            const bool c = z.hzv < t1;
+            const float nhbf = z.hbf + z.fstz;
+            const float nhzv = fabsf(nhbf) <= hz ? cross_at(nhbf, z.zeta_c, z.czr) : INFINITY;
+            if (c) {
+                z.lz = z.hzv;
+                z.mz += z.stz;
+                z.hbf = nhbf;
+                z.hzv = nhzv;
+            }
+            w2[r] = fminf(t1, z.hzv) - fmaxf(t0, z.lz);
+            ok2[r] = c && w2[r] > 0.0f && (unsigned)z.mz < (unsigned)nz;
+            const unsigned off = !ok2[r] ? 0u : (SZ == 1 ? (unsigned)z.mz : (unsigned)z.mz * (unsigned)sz);
+            v2[r] = col[off];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const acc_t<T> t = fma_acc(w[r], to_acc(v[r]), acc[r]);
+            acc[r] = ok[r] ? t : acc[r];
+            const acc_t<T> t2 = fma_acc(w2[r], to_acc(v2[r]), acc[r]);
+            acc[r] = ok2[r] ? t2 : acc[r];
+        }
+        // further crossings inside the piece (steep rays only)
+#pragma unroll
+        for (int r = 0; r < R; ++r) zwalk_steps<T, SZ>(zs[r], col, sz, nz, hz, t0, t1, acc[r]);
         if (hx == t1) {
             hx += 1.0f;
             base += sxi;

@@ -79,7 +79,9 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
     const int64_t rest = L / fg.ncg;
     const int k = (int)(rest % fg.nviews);
     const int band = (int)(rest / fg.nviews);
-    const int iu = cg * FWD_COLS + (int)(threadIdx.x >> 6);
+    // the wavefront's column, made provably uniform so that the in-plane walk
+    // (a function of the column) runs on scalar registers and branches
+    const int iu = cg * FWD_COLS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
     const ViewParam vp = g.views[k];
 
@@ -116,8 +118,12 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
     }
     if (col_ok) {
         A s[R];
-        trace_rays<TV, R>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc, czr,
-                             s);
+        if (sz == 1)
+            trace_rays<TV, R, 1>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc,
+                                 czr, s);
+        else
+            trace_rays<TV, R, 0>(base, sxi, seta, sz, nxi, neta, g.nz, hxi, heta, g.hz, cp.eta_c, cp.inv_a, cp.a, zc,
+                                 czr, s);
 #pragma unroll
         for (int r = 0; r < R; ++r) p[r] = (A)Ls[r] * s[r];
     } else {
