@@ -27,7 +27,7 @@ namespace kct {
 
 constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
 constexpr int CH_COLS = 48, CH_ROWS = 40;  // staged shadow chunk
-constexpr int NH = 4;                      // detector columns held in registers at once
+constexpr int NH = 2;                      // detector columns held in registers at once
 
 struct ColStage {  // per staged detector column: in-plane ray parameters
     float eta_c, inv_a, tcv;
