@@ -130,6 +130,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
     const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (centred index)
     const float zz0 = mbz0 + g.zc;         // the same plane as a height above the source plane
     const float vofs = -g.off_v * g.inv_dv + g.cv;
+    const float vofs_lo = vofs - 0.01f, vofs_hi = vofs + 0.01f;
     const int vmax = cv0 + nrow - 1;
     for (int c0 = ha; c0 <= hb; c0 += NH) {
         // xi-intervals of up to NH hit columns, and the range of T = tcv + xi gz
@@ -153,19 +154,20 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         // planes at heights [zz, zz + 1] only if qz lies in [zz, zz + 1] / [Tmin, Tmax].
         const float ra = __builtin_amdgcn_rcpf(tmax) * g.inv_dv, rb = __builtin_amdgcn_rcpf(tmin) * g.inv_dv;
         float pa = zz0 * ra, pb = zz0 * rb;
+        float mb = mbz0;  // lower plane of voxel j (exact: an integer or half-integer)
 #pragma unroll
         for (int j = 0; j < TZ; ++j) {
             const float zz1 = zz0 + (float)(j + 1);
             const float na = zz1 * ra, nb = zz1 * rb;
-            const float vlo = fminf(pa, pb) + vofs, vhi = fmaxf(na, nb) + vofs;
+            // the row offset and the 0.01-row margins in one constant each
+            const float vlo = fminf(pa, pb) + vofs_lo, vhi = fmaxf(na, nb) + vofs_hi;
             pa = na;
             pb = nb;
+            const float mb1 = mb + 1.0f;
             if (j < nzb) {
-                int va = (int)ceilf(vlo - 0.01f), vb = (int)floorf(vhi + 0.01f);
+                int va = (int)ceilf(vlo), vb = (int)floorf(vhi);
                 va = va < cv0 ? cv0 : va;
                 vb = vb > vmax ? vmax : vb;
-                const float mb = mbz0 + (float)j;
-                const float mb1 = mb + 1.0f;
                 for (int v = va; v <= vb; ++v) {
                     const PixStage<A> *prow = s_pix + (v - cv0) * CH_COLS + (c0 - cu0);
 #pragma unroll
@@ -181,6 +183,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
                     }
                 }
             }
+            mb = mb1;
         }
     }
 }
