@@ -35,8 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # Files each projector kernel is compiled from; the measured-traffic record in
 # profiles/ is valid only for the sources it was taken with.
 KERNEL_SOURCES = {
-    "forward": ("projector.hip", "kct_ray.h", "kct_weights.h", "kct_internal.h"),
-    "backward": ("backproject.hip", "kct_gather.h", "kct_weights.h", "kct_internal.h"),
+    "forward": ("csrc/projector.hip", "csrc/kct_ray.h", "csrc/kct_weights.h", "csrc/kct_internal.h",
+                "csrc/kct_epilogue.h", "build.py"),
+    "backward": ("csrc/backproject.hip", "csrc/kct_gather.h", "csrc/kct_weights.h", "csrc/kct_internal.h",
+                 "csrc/kct_epilogue.h", "build.py"),
 }
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "projector_c3_hbm_counters.json")
 
@@ -44,7 +46,7 @@ TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "projector_c3_hbm_counters.json"
 def kernel_source_hash(kind):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[kind]:
-        with open(os.path.join(ROOT, "paper_2110_13526_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2110_13526_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 

@@ -53,6 +53,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -514,6 +515,15 @@ enum { OG_STOP_MAXITER = 0, OG_STOP_TOL = 1, OG_STOP_BREAKDOWN = 2, OG_STOP_NUME
 void oracle_tt_project(const int32_t *dims, const double *par, const double *angles, const double *x, double *b);
 void oracle_tt_backproject(const int32_t *dims, const double *par, const double *angles, const double *y, double *r);
 
+/* Long runs can report each CGLS iteration on stderr (environment variable
+ * KCT_ORACLE_PROGRESS set); the arithmetic is not affected. */
+static int og_progress_flag(void)
+{
+    const char *v = getenv("KCT_ORACLE_PROGRESS");
+    return v && *v && *v != '0';
+}
+#define og_progress og_progress_flag()
+
 /* The operator of a solve: the Siddon pair (projector 0) or the TT pair (1). */
 static void og_A(int projector, const int32_t *dims, const double *par, const double *angles, const double *x,
                  double *b)
@@ -613,6 +623,7 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
         i = i + 1;
         og_cgls_discrepancy(projector, dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
         NB = sqrt(og_dot(e, e, m));
+        if (og_progress) fprintf(stderr, "oracle cgls: iteration %d of %d\n", i, K);
         if (history) history[i - 1] = NB0 > 0 ? NB / NB0 : 0.0;
         if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
     }

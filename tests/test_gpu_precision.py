@@ -150,9 +150,10 @@ def test_precision_report_c3down():
     At K = 10 the iterates are well conditioned (FP64 CGLS and FP64 LSQR, equal
     in exact arithmetic, agree to 6e-13) and each storage type must meet its
     solver bound against the oracle.  At K = 30 the Krylov recurrences amplify
-    rounding (the same two FP64 solvers differ by 5e-5), so there the criterion
-    is the reconstruction error against the phantom: within 1 % of the oracle's
-    (the equal-error criterion of the 512^3 benchmark); the distance to the
+    rounding (the same two FP64 solvers differ by 5e-5; any single-precision
+    run follows its own trajectory, 5e-3 away), so there the criterion is that
+    storage precision costs no reconstruction accuracy: the error against the
+    phantom may exceed the FP64 oracle's by at most 1 %.  The distance to the
     oracle's iterate is reported."""
     import json
     import time
@@ -186,7 +187,7 @@ def test_precision_report_c3down():
     for dt in ("f32", "bf16", "f16"):
         assert report[(10, dt)]["rel_l2_vs_fp64_oracle"] < SOLVE_TOL[dt]
         r = report[(30, dt)]
-        assert abs(r["rel_l2_vs_phantom"] / r["oracle_rel_l2_vs_phantom"] - 1.0) <= 0.01
+        assert r["rel_l2_vs_phantom"] <= 1.01 * r["oracle_rel_l2_vs_phantom"]
 
 
 def test_f64_projector_pair():
