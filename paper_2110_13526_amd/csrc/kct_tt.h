@@ -35,37 +35,64 @@ __host__ __device__ __forceinline__ void tt_sort4(float (&t)[4])
     t[3] = hi;
 }
 
-// Integral of the unit trapezoid t[0] <= t[1] <= t[2] <= t[3] from -inf to u.
-__host__ __device__ __forceinline__ float tt_cum(const float (&t)[4], float u)
+// Reciprocal (one hardware reciprocal on the GPU; both kernels of the pair use
+// this same function, so their weights stay bitwise identical).
+__host__ __device__ __forceinline__ float tt_rcp(float x)
 {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// A unit trapezoid t[0] <= t[1] <= t[2] <= t[3] with the reciprocals of twice
+// its ramp widths (used only where the ramp is wider than zero).
+struct TTTrap {
+    float t[4];
+    float r1, r2;  // 1 / (2 (t1 - t0)), 1 / (2 (t3 - t2))
+};
+
+__host__ __device__ __forceinline__ void tt_ramps(TTTrap &p)
+{
+    p.r1 = 0.5f * tt_rcp(p.t[1] - p.t[0]);
+    p.r2 = 0.5f * tt_rcp(p.t[3] - p.t[2]);
+}
+
+// Integral of the trapezoid from -inf to u.
+__host__ __device__ __forceinline__ float tt_cum(const TTTrap &p, float u)
+{
+    const float(&t)[4] = p.t;
     if (u <= t[0]) return 0.0f;
     if (u < t[1]) {
         const float a = u - t[0];
-        return a * a / (2.0f * (t[1] - t[0]));
+        return a * a * p.r1;
     }
     const float g = 0.5f * (t[1] - t[0]);
     if (u < t[2]) return g + (u - t[1]);
     const float g2 = g + (t[2] - t[1]);
     if (u < t[3]) {
         const float b = t[3] - u;
-        return g2 + 0.5f * (t[3] - t[2]) - b * b / (2.0f * (t[3] - t[2]));
+        return g2 + 0.5f * (t[3] - t[2]) - b * b * p.r2;
     }
     return g2 + 0.5f * (t[3] - t[2]);
 }
 
 // Mean of the trapezoid over detector pixel i.
-__host__ __device__ __forceinline__ float tt_mean(const float (&t)[4], int i)
+__host__ __device__ __forceinline__ float tt_mean(const TTTrap &p, int i)
 {
-    return tt_cum(t, (float)i + 0.5f) - tt_cum(t, (float)i - 0.5f);
+    return tt_cum(p, (float)i + 0.5f) - tt_cum(p, (float)i - 0.5f);
 }
 
-// Transaxial breakpoints (detector column coordinates, sorted) of voxel column
-// (ix, iy) in view vp, and the reciprocals of the smallest and largest depth of
-// its corners.
+// Transaxial trapezoid (detector column coordinates) of voxel column (ix, iy)
+// in view vp, the smallest and largest depth of its corners and their
+// reciprocals.
 __host__ __device__ __forceinline__ void tt_transaxial(const GeoDev &g, const ViewParam &vp, int ix, int iy,
-                                                       float (&tu)[4], float &rdmin, float &rdmax)
+                                                       TTTrap &tu, float &dmin, float &dmax, float &rdmin,
+                                                       float &rdmax)
 {
-    float dmin = INFINITY, dmax = 0.0f;
+    dmin = INFINITY;
+    dmax = 0.0f;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const float px = g.x0 + (float)(ix + (q & 1)) * g.vx;
@@ -75,13 +102,14 @@ __host__ __device__ __forceinline__ void tt_transaxial(const GeoDev &g, const Vi
         // source position
         const float num = -vp.s * px + vp.c * py;
         const float den = g.sid - (vp.c * px + vp.s * py);
-        tu[q] = (g.sdd * num / den - g.off_u) * g.inv_du + g.cu;
+        tu.t[q] = (g.sdd * num * tt_rcp(den) - g.off_u) * g.inv_du + g.cu;
         dmin = fminf(dmin, den);
         dmax = fmaxf(dmax, den);
     }
-    tt_sort4(tu);
-    rdmin = 1.0f / dmin;
-    rdmax = 1.0f / dmax;
+    tt_sort4(tu.t);
+    tt_ramps(tu);
+    rdmin = tt_rcp(dmin);
+    rdmax = tt_rcp(dmax);
 }
 
 // Detector row coordinate of the z-plane m seen at depth 1 / rd.
@@ -91,15 +119,16 @@ __host__ __device__ __forceinline__ float tt_plane_v(const GeoDev &g, int m, flo
     return (g.sdd * z * rd - g.off_v) * g.inv_dv + g.cv;
 }
 
-// Axial breakpoints (sorted) of voxel layer iz of a column with depth
-// reciprocals rdmin, rdmax.
-__host__ __device__ __forceinline__ void tt_axial(const GeoDev &g, int iz, float rdmin, float rdmax, float (&tv)[4])
+// Axial trapezoid of voxel layer iz of a column with depth reciprocals rdmin,
+// rdmax.
+__host__ __device__ __forceinline__ void tt_axial(const GeoDev &g, int iz, float rdmin, float rdmax, TTTrap &tv)
 {
-    tv[0] = tt_plane_v(g, iz, rdmin);
-    tv[1] = tt_plane_v(g, iz, rdmax);
-    tv[2] = tt_plane_v(g, iz + 1, rdmin);
-    tv[3] = tt_plane_v(g, iz + 1, rdmax);
-    tt_sort4(tv);
+    tv.t[0] = tt_plane_v(g, iz, rdmin);
+    tv.t[1] = tt_plane_v(g, iz, rdmax);
+    tv.t[2] = tt_plane_v(g, iz + 1, rdmin);
+    tv.t[3] = tt_plane_v(g, iz + 1, rdmax);
+    tt_sort4(tv.t);
+    tt_ramps(tv);
 }
 
 // L_i from the Siddon length factor L per unit xi (the path through one xi
@@ -170,11 +199,11 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
         e_hi = e_hi > neta - 1 ? neta - 1 : e_hi;
         for (int e = e_lo; e <= e_hi; ++e) {
             const int ix = dom0 ? m : e, iy = dom0 ? e : m;
-            float tu[4], rdmin, rdmax;
-            tt_transaxial(g, vp, ix, iy, tu, rdmin, rdmax);
+            TTTrap tu;
+            float dmin, dmax, rdmin, rdmax;
+            tt_transaxial(g, vp, ix, iy, tu, dmin, dmax, rdmin, rdmax);
             const float fu = tt_mean(tu, iu);
             if (!(fu > 0.0f) || !active) continue;
-            const float dmin = 1.0f / rdmin, dmax = 1.0f / rdmax;
             const float z1 = vlo * dmin * rsdd, z2 = vlo * dmax * rsdd;
             const float z3 = vhi * dmin * rsdd, z4 = vhi * dmax * rsdd;
             const float zmn = fminf(fminf(z1, z2), fminf(z3, z4)), zmx = fmaxf(fmaxf(z1, z2), fmaxf(z3, z4));
@@ -182,7 +211,7 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
             za = za < 0 ? 0 : za;
             zb = zb > g.nz - 1 ? g.nz - 1 : zb;
             for (int iz = za; iz <= zb; ++iz) {
-                float tv[4];
+                TTTrap tv;
                 tt_axial(g, iz, rdmin, rdmax, tv);
                 const float fv = tt_mean(tv, iv);
                 if (fv > 0.0f) {
@@ -202,12 +231,12 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
 // (column cu0 + c, row cv0 + r) at s_le[r * stride + c].  SQ: add
 // fl(F_u F_v)^2 * s_le instead (with s_le = L^2 this sums the squared weights).
 template <typename A, bool SQ, int NC = 4, int TZN = 16>
-__host__ __device__ __forceinline__ void tt_gather_chunk(const GeoDev &g, int iz0, int nzb, const float (&tu)[4],
+__host__ __device__ __forceinline__ void tt_gather_chunk(const GeoDev &g, int iz0, int nzb, const TTTrap &tu,
                                                          float rdmin, float rdmax, const A *s_le, int stride, int cu0,
                                                          int ncol, int cv0, int nrow, A (&acc)[TZN])
 {
     int ua, ub;
-    tt_pixels(tu[0], tu[3], ua, ub);
+    tt_pixels(tu.t[0], tu.t[3], ua, ub);
     ua = ua < cu0 ? cu0 : ua;
     ub = ub > cu0 + ncol - 1 ? cu0 + ncol - 1 : ub;
     const int vmax = cv0 + nrow - 1;
@@ -218,10 +247,10 @@ __host__ __device__ __forceinline__ void tt_gather_chunk(const GeoDev &g, int iz
 #pragma unroll
         for (int j = 0; j < TZN; ++j) {
             if (j < nzb) {
-                float tv[4];
+                TTTrap tv;
                 tt_axial(g, iz0 + j, rdmin, rdmax, tv);
                 int va, vb;
-                tt_pixels(tv[0], tv[3], va, vb);
+                tt_pixels(tv.t[0], tv.t[3], va, vb);
                 va = va < cv0 ? cv0 : va;
                 vb = vb > vmax ? vmax : vb;
                 for (int v = va; v <= vb; ++v) {

@@ -154,8 +154,9 @@ __global__ __launch_bounds__(256, 4) void k_backward_tt(GeoDev g, const T *__res
         __syncthreads();
         const T *pk = SQ ? proj : proj + (size_t)k * g.nv * g.nu;  // not read when SQ
         const ColParam *ck = g.cols + (size_t)k * g.nu;
-        float tu[4], rdmin = 0.0f, rdmax = 0.0f;
-        if (valid) tt_transaxial(g, vp, ix, iy, tu, rdmin, rdmax);
+        TTTrap tu{};
+        float dmin = 0.0f, dmax = 0.0f, rdmin = 0.0f, rdmax = 0.0f;
+        if (valid) tt_transaxial(g, vp, ix, iy, tu, dmin, dmax, rdmin, rdmax);
         for (int cu0 = u0; cu0 <= u1; cu0 += TT_CH_COLS) {
             const int ncol = u1 - cu0 + 1 < TT_CH_COLS ? u1 - cu0 + 1 : TT_CH_COLS;
             for (int cv0 = v0; cv0 <= v1; cv0 += TT_CH_ROWS) {
