@@ -187,7 +187,8 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
         // The current z-cell of every row first, with the R loads issued
         // together (a lane without a contribution reads element 0 of the column,
         // which exists, and keeps its sum), then the z-cells entered inside the
-        // piece: the same additions in the same order as zwalk_piece.
+        // piece: the same additions in the same order as a walk that handles one
+        // z-cell at a time.
         float w[R];
         bool ok[R];
         T v[R];
