@@ -170,6 +170,15 @@ def main():
     t_bwd = timed(lambda: kct.backproject(G, b, out=vbuf), 3)
     log(f"[bench] forward {t_fwd * 1e3:.2f} ms, backward {t_bwd * 1e3:.2f} ms per launch")
 
+    # measured STREAM triad a = b + s c on 2^28-element FP32 arrays (3 GiB moved per launch)
+    ta = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    tb_ = torch.ones_like(ta)
+    tc_ = torch.ones_like(ta)
+    t_triad = timed(lambda: torch.add(tb_, tc_, alpha=0.5, out=ta), 5)
+    triad_gbs = 3.0 * ta.numel() * 4 / t_triad / 1e9
+    del ta, tb_, tc_
+    log(f"[bench] STREAM triad {triad_gbs:.0f} GB/s")
+
     # nonzeros of A (exact count of the oracle on evenly spaced views, scaled)
     import oracle
     step = max(1, g.n_views // args.nnz_views)
@@ -184,6 +193,7 @@ def main():
     tb = measured_traffic_bytes(dominant, args.config, args.dtype)
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4),
+                "stream_triad_GBs": round(triad_gbs, 1), "frac_of_stream": round(ach / triad_gbs, 4),
                 "traffic": None if tb is None else round(tb / t_dom / 1e9, 1),
                 "traffic_bytes_per_launch": None if tb is None else float(f"{tb:.4g}"),
                 "kernel": dominant,
