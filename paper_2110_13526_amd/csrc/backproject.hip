@@ -43,7 +43,6 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
     __shared__ PixStage<A> s_pix[CH_ROWS * CH_COLS];
     __shared__ ColStage s_col[CH_COLS];
-    __shared__ int s_fp[4];
 
     // XCD-aware brick assignment
     const int nb = nbx * nby * nbz;
@@ -73,8 +72,11 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
-        // 1. shadow of the brick: lanes 0..7 of wave 0 project one corner each
-        if (threadIdx.x < 64) {
+        // 1. shadow of the brick: in every wavefront lanes 0..7 project one
+        //    corner each and the bounds are combined across those lanes, so
+        //    each wavefront holds them without a barrier (the same numbers in all)
+        int u0, u1, v0, v1;
+        {
             const int c = threadIdx.x & 7;
             float fu, fv;
             project_point(g, vp, (c & 1) ? wx1 : wx0, (c & 2) ? wy1 : wy0, (c & 4) ? wz1 : wz0, fu, fv);
@@ -85,18 +87,13 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 vmin = fminf(vmin, __shfl_xor(vmin, off, 8));
                 vmax = fmaxf(vmax, __shfl_xor(vmax, off, 8));
             }
-            if (threadIdx.x == 0) {
-                int u0 = (int)floorf(umin) - 1, u1 = (int)ceilf(umax) + 1;
-                int v0 = (int)floorf(vmin) - 1, v1 = (int)ceilf(vmax) + 1;
-                s_fp[0] = u0 < 0 ? 0 : u0;
-                s_fp[1] = u1 > g.nu - 1 ? g.nu - 1 : u1;
-                s_fp[2] = v0 < 0 ? 0 : v0;
-                s_fp[3] = v1 > g.nv - 1 ? g.nv - 1 : v1;
-            }
+            const int a0 = (int)floorf(umin) - 1, a1 = (int)ceilf(umax) + 1;
+            const int b0 = (int)floorf(vmin) - 1, b1 = (int)ceilf(vmax) + 1;
+            u0 = __builtin_amdgcn_readfirstlane(a0 < 0 ? 0 : a0);
+            u1 = __builtin_amdgcn_readfirstlane(a1 > g.nu - 1 ? g.nu - 1 : a1);
+            v0 = __builtin_amdgcn_readfirstlane(b0 < 0 ? 0 : b0);
+            v1 = __builtin_amdgcn_readfirstlane(b1 > g.nv - 1 ? g.nv - 1 : b1);
         }
-        __syncthreads();
-        const int u0 = s_fp[0], u1 = s_fp[1], v0 = s_fp[2], v1 = s_fp[3];
-        __syncthreads();
         const T *pk = SQ ? proj : proj + (size_t)k * g.nv * g.nu;  // not read when SQ
         const ColParam *ck = g.cols + (size_t)k * g.nu;
         for (int cu0 = u0; cu0 <= u1; cu0 += CH_COLS) {

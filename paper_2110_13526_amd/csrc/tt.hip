@@ -104,7 +104,6 @@ __global__ __launch_bounds__(256, 4) void k_backward_tt(GeoDev g, const T *__res
     using A = acc_t<T>;
     constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
     __shared__ A s_le[TT_CH_ROWS * TT_CH_COLS];
-    __shared__ int s_fp[4];
 
     const int nb = nbx * nby * nbz;
     const int w = blockIdx.x;
@@ -128,8 +127,12 @@ __global__ __launch_bounds__(256, 4) void k_backward_tt(GeoDev g, const T *__res
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
-        // shadow of the brick (the footprint never leaves the projected corners' range)
-        if (threadIdx.x < 64) {
+        // shadow of the brick (the footprint never leaves the projected corners'
+        // range): in every wavefront lanes 0..7 project one corner each and the
+        // bounds are combined across those lanes, so each wavefront holds them
+        // without a barrier (the same numbers in all)
+        int u0, u1, v0, v1;
+        {
             const int c = threadIdx.x & 7;
             float fu, fv;
             project_point(g, vp, (c & 1) ? wx1 : wx0, (c & 2) ? wy1 : wy0, (c & 4) ? wz1 : wz0, fu, fv);
@@ -140,18 +143,13 @@ __global__ __launch_bounds__(256, 4) void k_backward_tt(GeoDev g, const T *__res
                 vmin = fminf(vmin, __shfl_xor(vmin, off, 8));
                 vmax = fmaxf(vmax, __shfl_xor(vmax, off, 8));
             }
-            if (threadIdx.x == 0) {
-                int u0 = (int)floorf(umin) - 1, u1 = (int)ceilf(umax) + 1;
-                int v0 = (int)floorf(vmin) - 1, v1 = (int)ceilf(vmax) + 1;
-                s_fp[0] = u0 < 0 ? 0 : u0;
-                s_fp[1] = u1 > g.nu - 1 ? g.nu - 1 : u1;
-                s_fp[2] = v0 < 0 ? 0 : v0;
-                s_fp[3] = v1 > g.nv - 1 ? g.nv - 1 : v1;
-            }
+            const int a0 = (int)floorf(umin) - 1, a1 = (int)ceilf(umax) + 1;
+            const int b0 = (int)floorf(vmin) - 1, b1 = (int)ceilf(vmax) + 1;
+            u0 = __builtin_amdgcn_readfirstlane(a0 < 0 ? 0 : a0);
+            u1 = __builtin_amdgcn_readfirstlane(a1 > g.nu - 1 ? g.nu - 1 : a1);
+            v0 = __builtin_amdgcn_readfirstlane(b0 < 0 ? 0 : b0);
+            v1 = __builtin_amdgcn_readfirstlane(b1 > g.nv - 1 ? g.nv - 1 : b1);
         }
-        __syncthreads();
-        const int u0 = s_fp[0], u1 = s_fp[1], v0 = s_fp[2], v1 = s_fp[3];
-        __syncthreads();
         const T *pk = SQ ? proj : proj + (size_t)k * g.nv * g.nu;  // not read when SQ
         const ColParam *ck = g.cols + (size_t)k * g.nu;
         TTTrap tu{};
