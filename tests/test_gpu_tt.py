@@ -3,8 +3,10 @@ FP64 oracle, through the C ABI (Section 3's projector model; the projector of
 the experiments in Section 4).
 
 Tolerances as for the Siddon pair: relative L2 error 1e-5 for single-precision
-projections and backprojections, 1e-4 for FP32 solver iterates after K
-iterations; double-precision projections agree with the oracle to 1e-12.
+projections and backprojections (also with double storage, whose weights are
+the same single-precision numbers; its adjoint identity holds to 1e-12), plus
+one storage rounding for BF16 / FP16, and 1e-4 for FP32 solver iterates after K
+iterations.
 """
 import numpy as np
 import pytest
@@ -182,3 +184,43 @@ def test_cgls_tikhonov_and_recompute(c1_tt):
     ref = oracle.cgls(g, b.astype(np.float64), 8, recompute_every=3, projector="tt")
     x, _ = kct.cgls(G, to_dev(b), 8, recompute_every=3)
     assert rel(to_np(x), ref.x) < 1e-4
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("name", ["t16_offcenter", "c1"])
+def test_storage_types(name, dt):
+    """16-bit storage with FP32 accumulation: the oracle gets the storage-rounded
+    input, so the error is the FP32 weight bound plus one rounding of each output
+    (2^-9 for BF16, 2^-11 for FP16)."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dt]
+    bound = TOL + {"bf16": 2.0 ** -9, "f16": 2.0 ** -11}[dt]
+    g = SMALL[name]
+    G = tt_geometry(g)
+    x = torch.from_numpy(ki.phantom(g, 8, 5)).to(dev()).to(tdt)
+    b = kct.project(G, x)
+    assert b.dtype == tdt
+    eb = rel(to_np(b), oracle.tt_project(g, to_np(x)))
+    y = torch.from_numpy(np.abs(ki.random_projections(g, 9)).astype(np.float32)).to(dev()).to(tdt)
+    r = kct.backproject(G, y)
+    er = rel(to_np(r), oracle.tt_backproject(g, to_np(y)))
+    say(f"[tt] {name} {dt}: forward {eb:.3e} backward {er:.3e} (bound {bound:.3e})")
+    assert eb < bound and er < bound
+
+
+def test_autograd_pair_is_adjoint():
+    """The autograd wrappers on a TT geometry: the gradient of <A x, y> is A^T y."""
+    import paper_2110_13526_amd as kct
+    from paper_2110_13526_amd.autograd import project_fn
+    torch = torch_mod()
+    g = SMALL["t16_offcenter"]
+    G = tt_geometry(g)
+    x = torch.from_numpy(ki.random_volume(g, 3).astype(np.float64)).to(dev()).requires_grad_(True)
+    y = torch.from_numpy(ki.random_projections(g, 4).astype(np.float64)).to(dev())
+    (project_fn(G, x) * y).sum().backward()
+    ref = oracle.tt_backproject(g, to_np(y))
+    err = rel(to_np(x.grad), ref)
+    say(f"[tt] autograd grad vs oracle A^T y: {err:.3e}")
+    assert err < TOL
+    assert rel(to_np(x.grad), to_np(kct.backproject(G, y))) == 0.0
