@@ -153,11 +153,19 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         // Rows: inside these columns a ray of row height qz meets the z-cell with
         // planes at heights [zz, zz + 1] only if qz lies in [zz, zz + 1] / [Tmin, Tmax].
         const float ra = __builtin_amdgcn_rcpf(tmax) * g.inv_dv, rb = __builtin_amdgcn_rcpf(tmin) * g.inv_dv;
-        float pa = zz0 * ra, pb = zz0 * rb;
-        float mb = mbz0;  // lower plane of voxel j (exact: an integer or half-integer)
+        // The per-voxel plane heights below do not depend on the column group;
+        // computed here they stay short-lived (hoisted out of the group loop,
+        // all TZ of them would stay live through it).  The empty asm keeps the
+        // compiler from hoisting them.
+        float zzb = zz0, mbb = mbz0;
+#if defined(__HIP_DEVICE_COMPILE__)
+        asm volatile("" : "+v"(zzb), "+v"(mbb));
+#endif
+        float pa = zzb * ra, pb = zzb * rb;
+        float mb = mbb;  // lower plane of voxel j (exact: an integer or half-integer)
 #pragma unroll
         for (int j = 0; j < TZ; ++j) {
-            const float zz1 = zz0 + (float)(j + 1);
+            const float zz1 = zzb + (float)(j + 1);
             const float na = zz1 * ra, nb = zz1 * rb;
             // the row offset and the 0.01-row margins in one constant each
             const float vlo = fminf(pa, pb) + vofs_lo, vhi = fmaxf(na, nb) + vofs_hi;

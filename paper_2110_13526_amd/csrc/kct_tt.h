@@ -112,22 +112,31 @@ __host__ __device__ __forceinline__ void tt_transaxial(const GeoDev &g, const Vi
     rdmax = tt_rcp(dmax);
 }
 
-// Detector row coordinate of the z-plane m seen at depth 1 / rd.
-__host__ __device__ __forceinline__ float tt_plane_v(const GeoDev &g, int m, float rd)
+// Row scales of a voxel column: the detector row coordinate of height z seen
+// at depth D is z * (SDD / (D dv)) + row_offset, with ka for the nearest and kb
+// for the farthest corner depth (ka >= kb > 0).
+__host__ __device__ __forceinline__ void tt_row_scales(const GeoDev &g, float rdmin, float rdmax, float &ka, float &kb)
 {
-    const float z = g.z0 + (float)m * g.vz;
-    return (g.sdd * z * rd - g.off_v) * g.inv_dv + g.cv;
+    const float s = g.sdd * g.inv_dv;
+    ka = s * rdmin;
+    kb = s * rdmax;
 }
+__host__ __device__ __forceinline__ float tt_row_offset(const GeoDev &g) { return g.cv - g.off_v * g.inv_dv; }
 
-// Axial trapezoid of voxel layer iz of a column with depth reciprocals rdmin,
-// rdmax.
-__host__ __device__ __forceinline__ void tt_axial(const GeoDev &g, int iz, float rdmin, float rdmax, TTTrap &tv)
+// Axial trapezoid of voxel layer iz of a column with row scales ka, kb.  The
+// row coordinate grows with z at either scale, so the two images of the lower
+// plane lie below those of the upper plane and sorting needs only their
+// inner pair.
+__host__ __device__ __forceinline__ void tt_axial(const GeoDev &g, int iz, float ka, float kb, float off, TTTrap &tv)
 {
-    tv.t[0] = tt_plane_v(g, iz, rdmin);
-    tv.t[1] = tt_plane_v(g, iz, rdmax);
-    tv.t[2] = tt_plane_v(g, iz + 1, rdmin);
-    tv.t[3] = tt_plane_v(g, iz + 1, rdmax);
-    tt_sort4(tv.t);
+    const float zl = g.z0 + (float)iz * g.vz, zh = g.z0 + (float)(iz + 1) * g.vz;
+    const float la = __builtin_fmaf(zl, ka, off), lb = __builtin_fmaf(zl, kb, off);
+    const float ha = __builtin_fmaf(zh, ka, off), hb = __builtin_fmaf(zh, kb, off);
+    const float l1 = fmaxf(la, lb), h0 = fminf(ha, hb);
+    tv.t[0] = fminf(la, lb);
+    tv.t[1] = fminf(l1, h0);
+    tv.t[2] = fmaxf(l1, h0);
+    tv.t[3] = fmaxf(ha, hb);
     tt_ramps(tv);
 }
 
@@ -190,6 +199,7 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
     const float vlo = ((float)iv - 0.5f - g.cv) * g.dv + g.off_v;
     const float vhi = ((float)iv + 0.5f - g.cv) * g.dv + g.off_v;
     const float rsdd = 1.0f / g.sdd;
+    const float roff = tt_row_offset(g);
     for (int m = 0; m < nxi; ++m) {
         const float xl = (float)m - hxi, xh = xl + 1.0f;
         const float ea = a0 + a1 * xl, eb = a0 + a1 * xh, ec = b0 + b1 * xl, ed = b0 + b1 * xh;
@@ -204,6 +214,8 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
             tt_transaxial(g, vp, ix, iy, tu, dmin, dmax, rdmin, rdmax);
             const float fu = tt_mean(tu, iu);
             if (!(fu > 0.0f) || !active) continue;
+            float ka, kb;
+            tt_row_scales(g, rdmin, rdmax, ka, kb);
             const float z1 = vlo * dmin * rsdd, z2 = vlo * dmax * rsdd;
             const float z3 = vhi * dmin * rsdd, z4 = vhi * dmax * rsdd;
             const float zmn = fminf(fminf(z1, z2), fminf(z3, z4)), zmx = fmaxf(fmaxf(z1, z2), fmaxf(z3, z4));
@@ -212,7 +224,7 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
             zb = zb > g.nz - 1 ? g.nz - 1 : zb;
             for (int iz = za; iz <= zb; ++iz) {
                 TTTrap tv;
-                tt_axial(g, iz, rdmin, rdmax, tv);
+                tt_axial(g, iz, ka, kb, roff, tv);
                 const float fv = tt_mean(tv, iv);
                 if (fv > 0.0f) {
                     const TV xv = vol_z ? vol_z[((size_t)iy * g.nx + ix) * g.nz + iz]
@@ -240,7 +252,18 @@ __host__ __device__ __forceinline__ void tt_gather_chunk(const GeoDev &g, int iz
     ua = ua < cu0 ? cu0 : ua;
     ub = ub > cu0 + ncol - 1 ? cu0 + ncol - 1 : ub;
     const int vmax = cv0 + nrow - 1;
+    float ka, kb;
+    tt_row_scales(g, rdmin, rdmax, ka, kb);
+    const float roff = tt_row_offset(g);
     for (int c0 = ua; c0 <= ub; c0 += NC) {
+        // The axial trapezoids below do not depend on c0; computed inside the
+        // loop they stay short-lived (hoisted out, all TZN of them would be
+        // live at once and spill).  The empty asm keeps the compiler from
+        // hoisting them.
+        float kai = ka, kbi = kb;
+#if defined(__HIP_DEVICE_COMPILE__)
+        asm volatile("" : "+v"(kai), "+v"(kbi));
+#endif
         float fu[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) fu[c] = c0 + c <= ub ? tt_mean(tu, c0 + c) : 0.0f;
@@ -248,7 +271,7 @@ __host__ __device__ __forceinline__ void tt_gather_chunk(const GeoDev &g, int iz
         for (int j = 0; j < TZN; ++j) {
             if (j < nzb) {
                 TTTrap tv;
-                tt_axial(g, iz0 + j, rdmin, rdmax, tv);
+                tt_axial(g, iz0 + j, kai, kbi, roff, tv);
                 int va, vb;
                 tt_pixels(tv.t[0], tv.t[3], va, vb);
                 va = va < cv0 ? cv0 : va;

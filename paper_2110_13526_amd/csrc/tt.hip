@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void k_forward_tt(GeoDev g, const TV *__restri
 }
 
 template <typename T, int EPI>
-__global__ __launch_bounds__(256, 4) void k_backward_tt(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
+__global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward_tt(GeoDev g, const T *__restrict__ proj, T *__restrict__ out,
                                                         T *__restrict__ out_z, const Scalars *__restrict__ sc,
                                                         double *__restrict__ partials, const int *__restrict__ skip,
                                                         int nbx, int nby, int nbz, const float *__restrict__ aux)
