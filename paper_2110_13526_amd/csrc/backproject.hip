@@ -197,6 +197,7 @@ hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int cou
 int64_t backward_num_blocks(const GeoDev &g)
 {
     int nbx, nby, nbz;
+    if (g.projector == KCT_PROJECTOR_TT) return tt_backward_grid_dims(g, nbx, nby, nbz);
     bwd_grid(g, nbx, nby, nbz);
     return (int64_t)nbx * nby * nbz;
 }

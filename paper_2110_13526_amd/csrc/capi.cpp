@@ -41,6 +41,9 @@ int64_t num_partials(const Geometry *g)
     int64_t a = forward_num_blocks_r(g->dev, 1), b = backward_num_blocks(g->dev), c = stream_num_blocks();
     const int64_t t = tt_forward_num_blocks(g->dev);
     if (t > a) a = t;
+    int nbx, nby, nbz;
+    const int64_t tb = tt_backward_grid_dims(g->dev, nbx, nby, nbz);
+    if (tb > b) b = tb;
     int64_t m = a > b ? a : b;
     return m > c ? m : c;
 }

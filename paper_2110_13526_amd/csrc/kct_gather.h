@@ -25,7 +25,7 @@
 
 namespace kct {
 
-constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
+constexpr int BX = 16, BY = 16, TZ = 24;   // brick; BX * BY = 256 lanes
 constexpr int CH_COLS = 48, CH_ROWS = 40;  // staged shadow chunk
 constexpr int NH = 2;                      // detector columns held in registers at once
 

@@ -231,5 +231,6 @@ hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, i
 // finalize of every instance; kind: which grid produced the partials (BatchGrid)
 hipError_t launch_batch_finalize(const BatchInst *B, int count, int op, int kind, hipStream_t st);
 int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz);
+int64_t tt_backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz);
 
 }  // namespace kct

@@ -28,6 +28,7 @@ namespace kct {
 constexpr int TT_COLS = 4;                           // forward: detector columns per workgroup
 constexpr int TT_CH_COLS = 48, TT_CH_ROWS = 40;      // backward: staged shadow chunk
 constexpr int TT_NXCD = 8;
+constexpr int TT_TZ = 16;                            // backward: voxels per lane along z
 
 struct TTFwdGrid {
     int ncg, nbands, nviews;
@@ -45,6 +46,15 @@ __host__ __device__ __forceinline__ TTFwdGrid tt_fwd_grid(const GeoDev &g)
 }
 
 int64_t tt_forward_num_blocks(const GeoDev &g) { return tt_fwd_grid(g).nblocks; }
+
+// Backward grid: bricks of BX x BY x TT_TZ voxels.
+int64_t tt_backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz)
+{
+    nbx = (g.nx + BX - 1) / BX;
+    nby = (g.ny + BY - 1) / BY;
+    nbz = (g.nz + TT_TZ - 1) / TT_TZ;
+    return (int64_t)nbx * nby * nbz;
+}
 
 __device__ __forceinline__ double tt_block_sum(double v)
 {
@@ -111,8 +121,8 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int ix = bx * BX + (int)(threadIdx.x % BX);
     const int iy = by * BY + (int)(threadIdx.x / BX);
-    const int iz0 = bz * TZ;
-    const int nzb = g.nz - iz0 < TZ ? g.nz - iz0 : TZ;
+    const int iz0 = bz * TT_TZ;
+    const int nzb = g.nz - iz0 < TT_TZ ? g.nz - iz0 : TT_TZ;
     const bool valid = ix < g.nx && iy < g.ny;
 
     const int ex = (bx + 1) * BX < g.nx ? (bx + 1) * BX : g.nx;
@@ -121,9 +131,9 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
     const float wy0 = g.y0 + (float)(by * BY) * g.vy, wy1 = g.y0 + (float)ey * g.vy;
     const float wz0 = g.z0 + (float)iz0 * g.vz, wz1 = g.z0 + (float)(iz0 + nzb) * g.vz;
 
-    A acc[TZ];
+    A acc[TT_TZ];
 #pragma unroll
-    for (int j = 0; j < TZ; ++j) acc[j] = 0;
+    for (int j = 0; j < TT_TZ; ++j) acc[j] = 0;
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
     double sq = 0.0;
     if (valid) {
 #pragma unroll
-        for (int j = 0; j < TZ; ++j) {
+        for (int j = 0; j < TT_TZ; ++j) {
             if (j >= nzb) continue;
             const int iz = iz0 + j;
             const size_t vox = ((size_t)iz * g.ny + iy) * g.nx + ix;
@@ -225,7 +235,7 @@ static void launch_btt(const GeoDev &g, const T *proj, T *out, T *out_z, const S
                        const int *skip, const float *aux, hipStream_t st)
 {
     int nbx, nby, nbz;
-    const int64_t nb = backward_grid_dims(g, nbx, nby, nbz);
+    const int64_t nb = tt_backward_grid_dims(g, nbx, nby, nbz);
     hipLaunchKernelGGL((k_backward_tt<T, EPI>), dim3((unsigned)nb), dim3(256), 0, st, g, proj, out, out_z, sc,
                        partials, skip, nbx, nby, nbz, aux);
 }
