@@ -148,7 +148,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 }
 
 template <typename T, int EPI>
-__global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 4 : 2) void k_backward(GeoDev g, const T *__restrict__ proj,
+__global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : (EPI == BWD_PLAIN ? 4 : 5)) void k_backward(GeoDev g, const T *__restrict__ proj,
                                                                                 T *__restrict__ out,
                                                                                 T *__restrict__ out_z,
                                                                                 const Scalars *__restrict__ sc,
