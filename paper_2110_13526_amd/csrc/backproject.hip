@@ -33,7 +33,7 @@ __device__ __forceinline__ double bwd_block_sum(double v)
 
 // backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
 // backprojection into one volume; its partial sum goes to partials[w].
-template <typename T, int EPI>
+template <typename T, int EPI, int TZB>
 __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *__restrict__ proj,
                                                T *__restrict__ out, T *__restrict__ out_z,
                                                const Scalars *__restrict__ sc, double *__restrict__ partials,
@@ -50,8 +50,8 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     const int ix = bx * BX + (int)(threadIdx.x % BX);
     const int iy = by * BY + (int)(threadIdx.x / BX);
-    const int iz0 = bz * TZ;
-    const int nzb = g.nz - iz0 < TZ ? g.nz - iz0 : TZ;
+    const int iz0 = bz * TZB;
+    const int nzb = g.nz - iz0 < TZB ? g.nz - iz0 : TZB;
     const bool valid = ix < g.nx && iy < g.ny;
 
     // brick corners in world coordinates (clamped to the volume)
@@ -66,9 +66,9 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     const int pcell = parallel_cell(-g.zc, g.hz);
     const float pzadd = ((float)pcell - g.hz + 0.5f) + g.zc;
 
-    A acc[TZ];
+    A acc[TZB];
 #pragma unroll
-    for (int j = 0; j < TZ; ++j) acc[j] = 0;
+    for (int j = 0; j < TZB; ++j) acc[j] = 0;
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
@@ -134,7 +134,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     double sq = 0.0;
     if (valid) {
 #pragma unroll
-        for (int j = 0; j < TZ; ++j) {
+        for (int j = 0; j < TZB; ++j) {
             if (j >= nzb) continue;
             const int iz = iz0 + j;
             const size_t vox = ((size_t)iz * g.ny + iy) * g.nx + ix;
@@ -147,7 +147,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     }
 }
 
-template <typename T, int EPI>
+template <typename T, int EPI, int TZB>
 __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : (EPI == BWD_PLAIN ? 4 : 5)) void k_backward(GeoDev g, const T *__restrict__ proj,
                                                                                 T *__restrict__ out,
                                                                                 T *__restrict__ out_z,
@@ -158,24 +158,35 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : (EPI == BWD_PLAIN 
                                                                                 const float *__restrict__ aux)
 {
     if (skip && *skip) return;
-    backward_block<T, EPI>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux);
+    backward_block<T, EPI, TZB>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux);
 }
 
-static void bwd_grid(const GeoDev &g, int &nbx, int &nby, int &nbz)
+// Brick depth of a single backprojection: TZ_DEEP voxels per lane when the
+// volume still gives at least 5120 such bricks (four rounds of five workgroups
+// per compute unit), else TZ (small volumes need the workgroups more than the
+// shared setup).
+static int bwd_depth(const GeoDev &g)
+{
+    const int64_t deep = (int64_t)((g.nx + BX - 1) / BX) * ((g.ny + BY - 1) / BY) * ((g.nz + TZ_DEEP - 1) / TZ_DEEP);
+    return deep >= 5120 ? TZ_DEEP : TZ;
+}
+
+static void bwd_grid(const GeoDev &g, int tz, int &nbx, int &nby, int &nbz)
 {
     nbx = (g.nx + BX - 1) / BX;
     nby = (g.ny + BY - 1) / BY;
-    nbz = (g.nz + TZ - 1) / TZ;
+    nbz = (g.nz + tz - 1) / tz;
 }
 
+// Grid of the batched backprojection (bricks of depth TZ for every instance).
 int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz)
 {
-    bwd_grid(g, nbx, nby, nbz);
+    bwd_grid(g, TZ, nbx, nby, nbz);
     return (int64_t)nbx * nby * nbz;
 }
 
 // Batched r = A^T e with |r|^2 partials for every instance.
-__global__ __launch_bounds__(256, 4) void kb_backward(const BatchInst *__restrict__ B,
+__global__ __launch_bounds__(256, 5) void kb_backward(const BatchInst *__restrict__ B,
                                                       const int64_t *__restrict__ off, int count)
 {
     const int64_t w = blockIdx.x;
@@ -184,8 +195,8 @@ __global__ __launch_bounds__(256, 4) void kb_backward(const BatchInst *__restric
     if (bi->sc->done) return;
     const int64_t lw = w - off[i];
     if (lw >= (int64_t)bi->nbx * bi->nby * bi->nbz) return;  // padding of the instance's grid
-    backward_block<float, BWD_NORM>(bi->g, (int)lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx, bi->nby,
-                                    bi->nbz, nullptr);
+    backward_block<float, BWD_NORM, TZ>(bi->g, (int)lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx, bi->nby,
+                                        bi->nbz, nullptr);
 }
 
 hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st)
@@ -194,20 +205,30 @@ hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int cou
     return hipGetLastError();
 }
 
+// Workgroups (and partial sums) of a single backprojection with g: at most the
+// count of TZ-deep bricks.
 int64_t backward_num_blocks(const GeoDev &g)
 {
     int nbx, nby, nbz;
     if (g.projector == KCT_PROJECTOR_TT) return tt_backward_grid_dims(g, nbx, nby, nbz);
-    bwd_grid(g, nbx, nby, nbz);
+    bwd_grid(g, bwd_depth(g), nbx, nby, nbz);
     return (int64_t)nbx * nby * nbz;
 }
 
 template <typename T, int EPI>
 static void launch_bwd(const GeoDev &g, const T *proj, T *out, T *out_z, const Scalars *sc, double *partials,
-                       const int *skip, dim3 grid, int nbx, int nby, int nbz, const float *aux, hipStream_t st)
+                       const int *skip, const float *aux, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_backward<T, EPI>), grid, dim3(256), 0, st, g, proj, out, out_z, sc, partials, skip, nbx, nby,
-                       nbz, aux);
+    const int tz = bwd_depth(g);
+    int nbx, nby, nbz;
+    bwd_grid(g, tz, nbx, nby, nbz);
+    const dim3 grid((unsigned)(nbx * nby * nbz));
+    if (tz == TZ_DEEP)
+        hipLaunchKernelGGL((k_backward<T, EPI, TZ_DEEP>), grid, dim3(256), 0, st, g, proj, out, out_z, sc, partials,
+                           skip, nbx, nby, nbz, aux);
+    else
+        hipLaunchKernelGGL((k_backward<T, EPI, TZ>), grid, dim3(256), 0, st, g, proj, out, out_z, sc, partials, skip,
+                           nbx, nby, nbz, aux);
 }
 
 template <typename T>
@@ -215,28 +236,25 @@ hipError_t launch_backward(const GeoDev &g, const T *proj, T *out, T *out_z, int
                            double *partials, const int *skip, hipStream_t st, const float *aux)
 {
     if (g.projector == KCT_PROJECTOR_TT) return launch_backward_tt<T>(g, proj, out, out_z, epi, sc, partials, skip, st, aux);
-    int nbx, nby, nbz;
-    bwd_grid(g, nbx, nby, nbz);
-    const dim3 grid((unsigned)(nbx * nby * nbz));
     if constexpr (std::is_same<T, double>::value) {  // double storage: plain backprojection only
         if (epi != BWD_PLAIN) return hipErrorInvalidValue;
-        launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+        launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, aux, st);
     } else {
         switch (epi) {
-        case BWD_PLAIN: launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
-        case BWD_NORM: launch_bwd<T, BWD_NORM>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
-        case BWD_LSQR0: launch_bwd<T, BWD_LSQR0>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
-        case BWD_LSQR: launch_bwd<T, BWD_LSQR>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
-        case BWD_TIK: launch_bwd<T, BWD_TIK>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
-        case BWD_JACOBI: launch_bwd<T, BWD_JACOBI>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st); break;
+        case BWD_PLAIN: launch_bwd<T, BWD_PLAIN>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
+        case BWD_NORM: launch_bwd<T, BWD_NORM>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
+        case BWD_LSQR0: launch_bwd<T, BWD_LSQR0>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
+        case BWD_LSQR: launch_bwd<T, BWD_LSQR>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
+        case BWD_TIK: launch_bwd<T, BWD_TIK>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
+        case BWD_JACOBI: launch_bwd<T, BWD_JACOBI>(g, proj, out, out_z, sc, partials, skip, aux, st); break;
         default:
             if constexpr (std::is_same<T, float>::value) {  // the diagonal of A^T A is single precision
                 if (epi == BWD_DIAG) {
-                    launch_bwd<T, BWD_DIAG>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+                    launch_bwd<T, BWD_DIAG>(g, proj, out, out_z, sc, partials, skip, aux, st);
                     break;
                 }
                 if (epi == BWD_DIAG_INV) {
-                    launch_bwd<T, BWD_DIAG_INV>(g, proj, out, out_z, sc, partials, skip, grid, nbx, nby, nbz, aux, st);
+                    launch_bwd<T, BWD_DIAG_INV>(g, proj, out, out_z, sc, partials, skip, aux, st);
                     break;
                 }
             }

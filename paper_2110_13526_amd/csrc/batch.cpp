@@ -49,7 +49,8 @@ int64_t inst_m(const Geometry *g) { return (int64_t)g->dev.nviews * g->dev.nv * 
 int64_t inst_partials(const Geometry *g)
 {
     int64_t a = std::max(forward_num_blocks_r(g->dev, 1), forward_num_blocks_r(g->dev, 2));
-    int64_t b = backward_num_blocks(g->dev);
+    int nbx, nby, nbz;
+    int64_t b = backward_grid_dims(g->dev, nbx, nby, nbz);  // the batched backprojection's grid
     return std::max(std::max(a, b), stream_num_blocks());
 }
 

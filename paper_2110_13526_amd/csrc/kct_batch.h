@@ -15,7 +15,9 @@ __device__ __forceinline__ int batch_find(const int64_t *__restrict__ off, int c
         if (off[mid] <= w) lo = mid;
         else hi = mid;
     }
-    return lo;
+    // the same instance in every lane (w is the workgroup's): keep the
+    // instance's fields in scalar registers
+    return __builtin_amdgcn_readfirstlane(lo);
 }
 
 }  // namespace kct

@@ -25,7 +25,8 @@
 
 namespace kct {
 
-constexpr int BX = 16, BY = 16, TZ = 24;   // brick; BX * BY = 256 lanes
+constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
+constexpr int TZ_DEEP = 24;                // deeper bricks for large volumes (more voxels share a lane's setup)
 constexpr int CH_COLS = 48, CH_ROWS = 40;  // staged shadow chunk
 constexpr int NH = 2;                      // detector columns held in registers at once
 
@@ -101,10 +102,10 @@ __host__ __device__ __forceinline__ void column_interval(const ColStage &cs, flo
 // i = (column cu0 + c, row cv0 + r); s_pix[r * CH_COLS + c] describes ray i.
 // SQ: accumulate w_ij^2 * le instead of w_ij * le (with le = L^2 this sums the
 // squared weights, the diagonal of A^T A).
-template <typename A, bool SQ = false>
+template <typename A, bool SQ = false, int TZN = TZ>
 __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const ViewParam &vp, int ix, int iy, int iz0,
                                                       int nzb, const PixStage<A> *s_pix, const ColStage *s_col,
-                                                      int cu0, int ncol, int cv0, int nrow, A (&acc)[TZ])
+                                                      int cu0, int ncol, int cv0, int nrow, A (&acc)[TZN])
 {
     int ixi, ieta;
     float hxi, heta;
@@ -164,7 +165,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         float pa = zzb * ra, pb = zzb * rb;
         float mb = mbb;  // lower plane of voxel j (exact: an integer or half-integer)
 #pragma unroll
-        for (int j = 0; j < TZ; ++j) {
+        for (int j = 0; j < TZN; ++j) {
             const float zz1 = zzb + (float)(j + 1);
             const float na = zz1 * ra, nb = zz1 * rb;
             // the row offset and the 0.01-row margins in one constant each

@@ -28,7 +28,7 @@ namespace kct {
 constexpr int TT_COLS = 4;                           // forward: detector columns per workgroup
 constexpr int TT_CH_COLS = 48, TT_CH_ROWS = 40;      // backward: staged shadow chunk
 constexpr int TT_NXCD = 8;
-constexpr int TT_TZ = 16;                            // backward: voxels per lane along z
+constexpr int TT_TZ = TZ;                            // backward: voxels per lane along z
 
 struct TTFwdGrid {
     int ncg, nbands, nviews;
