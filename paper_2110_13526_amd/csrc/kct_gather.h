@@ -64,6 +64,16 @@ __host__ __device__ __forceinline__ void project_point(const GeoDev &g, const Vi
     fv = (pz * sc - g.off_v) * g.inv_dv + g.cv;
 }
 
+// Median of x, a and b: x clamped to the interval between a and b.
+__host__ __device__ __forceinline__ float med3f(float x, float a, float b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_fmed3f(x, a, b);
+#else
+    return fmaxf(fminf(x, a), fminf(fmaxf(x, a), b));
+#endif
+}
+
 // Candidate detector columns [ua, ub] of the voxel column whose in-plane centre
 // is (xc, yc): the projective image of its square, bounded around the image of
 // the centre (a bound with margin; the weight function decides).
@@ -184,7 +194,10 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
                         if (h < nh) {
                             const PixStage<A> p = prow[h];
                             const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
-                            const float w = fminf(hi[h], fmaxf(b0, b1)) - fmaxf(lo[h], fminf(b0, b1));
+                            // min(hi, max(b0, b1)) - max(lo, min(b0, b1)) wherever that is positive
+                            // (there hi > min(b0, b1) and lo < max(b0, b1), so clamping hi and lo to
+                            // [min, max] selects the same operands); elsewhere <= 0 like it
+                            const float w = med3f(hi[h], b0, b1) - med3f(lo[h], b0, b1);
                             // select instead of a branch: one record read, no divergent block
                             const A t = fma_acc(SQ ? w * w : w, p.le, acc[j]);
                             acc[j] = w > 0.0f ? t : acc[j];
