@@ -102,17 +102,30 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 const int nrow = v1 - cv0 + 1 < CH_ROWS ? v1 - cv0 + 1 : CH_ROWS;
                 // 2. stage the chunk: per pixel the z-parameters of its ray and L * e,
                 //    per column the in-plane parameters
-                for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
-                    const int r = t / ncol, c = t - r * ncol;
-                    const ColParam cp = ck[cu0 + c];
-                    const RowParam rp = g.rows[cv0 + r];
-                    const bool par = rp.inv_qz == 0.0f;
-                    PixStage<A> ps;
-                    ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
-                    ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
-                    const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
-                    ps.le = SQ ? L * L : L * to_acc(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
-                    s_pix[r * CH_COLS + c] = ps;
+                //    (pixel t = r * ncol + c; t steps by 256: r by dr, c by dc, with carry)
+                {
+                    int r = (int)threadIdx.x / ncol, c = (int)threadIdx.x - r * ncol;
+                    const int dr = 256 / ncol, dc = 256 - dr * ncol;
+                    for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
+                        // the projection value first: its load overlaps the parameter loads
+                        // (offsets within one view fit in 32 bits: a projection has < 2^31 rays)
+                        const A ev = SQ ? (A)0 : to_acc(pk[(unsigned)((cv0 + r) * g.nu + cu0 + c)]);
+                        const ColParam cp = ck[cu0 + c];
+                        const RowParam rp = g.rows[cv0 + r];
+                        const bool par = rp.inv_qz == 0.0f;
+                        PixStage<A> ps;
+                        ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
+                        ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
+                        const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
+                        ps.le = SQ ? L * L : L * ev;
+                        s_pix[r * CH_COLS + c] = ps;
+                        r += dr;
+                        c += dc;
+                        if (c >= ncol) {
+                            c -= ncol;
+                            ++r;
+                        }
+                    }
                 }
                 if (threadIdx.x < ncol) {
                     const ColParam cp = ck[cu0 + threadIdx.x];

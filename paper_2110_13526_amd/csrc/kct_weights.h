@@ -38,11 +38,17 @@ __host__ __device__ __forceinline__ float cross_at(float mb, float c, float inv)
 __host__ __device__ __forceinline__ float zeta_centre(float qz, float tcv, float zc) { return qz * tcv - zc; }
 __host__ __device__ __forceinline__ float zeta_inv_slope(float inv_qz, float kz) { return inv_qz * kz; }
 
-// Length of the ray in mm per unit of xi.
+// Length of the ray in mm per unit of xi.  On the GPU the hardware square root
+// (within 1 ulp; one instruction instead of the correctly rounded sequence):
+// every kernel takes L from this function, so L stays one number per ray.
 __host__ __device__ __forceinline__ float ray_length_per_xi(float lxy2, float qz, float gp)
 {
     float t = qz * gp;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(lxy2 + t * t);
+#else
     return sqrtf(lxy2 + t * t);
+#endif
 }
 
 // The cell (0-based) that a ray parallel to an axis' planes lies in.
