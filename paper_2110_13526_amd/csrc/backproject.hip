@@ -41,8 +41,9 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 {
     using A = acc_t<T>;
     constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
-    __shared__ PixStage<A> s_pix[CH_ROWS * CH_COLS];
-    __shared__ ColStage s_col[CH_COLS];
+    constexpr int CHC = ch_cols(TZB);
+    __shared__ PixStage<A> s_pix[CH_ROWS * CHC];
+    __shared__ ColStage s_col[CHC];
 
     // XCD-aware brick assignment
     const int nb = nbx * nby * nbz;
@@ -96,8 +97,8 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
         }
         const T *pk = SQ ? proj : proj + (size_t)k * g.nv * g.nu;  // not read when SQ
         const ColParam *ck = g.cols + (size_t)k * g.nu;
-        for (int cu0 = u0; cu0 <= u1; cu0 += CH_COLS) {
-            const int ncol = u1 - cu0 + 1 < CH_COLS ? u1 - cu0 + 1 : CH_COLS;
+        for (int cu0 = u0; cu0 <= u1; cu0 += CHC) {
+            const int ncol = u1 - cu0 + 1 < CHC ? u1 - cu0 + 1 : CHC;
             for (int cv0 = v0; cv0 <= v1; cv0 += CH_ROWS) {
                 const int nrow = v1 - cv0 + 1 < CH_ROWS ? v1 - cv0 + 1 : CH_ROWS;
                 // 2. stage the chunk: per pixel the z-parameters of its ray and L * e,
@@ -118,7 +119,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                         ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
                         const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
                         ps.le = SQ ? L * L : L * ev;
-                        s_pix[r * CH_COLS + c] = ps;
+                        s_pix[r * CHC + c] = ps;
                         r += dr;
                         c += dc;
                         if (c >= ncol) {
@@ -138,7 +139,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 }
                 __syncthreads();
                 // 3. gather
-                if (valid) gather_chunk<A, SQ>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
+                if (valid) gather_chunk<A, SQ, CHC>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
                 __syncthreads();
             }
         }
@@ -161,7 +162,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 }
 
 template <typename T, int EPI, int TZB>
-__global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : (EPI == BWD_PLAIN ? 4 : 5)) void k_backward(GeoDev g, const T *__restrict__ proj,
+__global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward(GeoDev g, const T *__restrict__ proj,
                                                                                 T *__restrict__ out,
                                                                                 T *__restrict__ out_z,
                                                                                 const Scalars *__restrict__ sc,
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : (EPI == BWD_PLAIN 
 }
 
 // Brick depth of a single backprojection: TZ_DEEP voxels per lane when the
-// volume still gives at least 5120 such bricks (four rounds of five workgroups
+// volume still gives at least 5120 such bricks (over three rounds of six workgroups
 // per compute unit), else TZ (small volumes need the workgroups more than the
 // shared setup).
 static int bwd_depth(const GeoDev &g)
@@ -199,7 +200,7 @@ int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz)
 }
 
 // Batched r = A^T e with |r|^2 partials for every instance.
-__global__ __launch_bounds__(256, 5) void kb_backward(const BatchInst *__restrict__ B,
+__global__ __launch_bounds__(256, 6) void kb_backward(const BatchInst *__restrict__ B,
                                                       const int64_t *__restrict__ off, int count)
 {
     const int64_t w = blockIdx.x;

@@ -14,7 +14,7 @@
 //      columns (shared by the TZ voxels), per voxel the candidate rows from
 //      the z-range of those rays, and for every candidate the exact weight of
 //      kct_weights.h.
-// The shadow is staged in chunks of at most CH_COLS x CH_ROWS pixels, so any
+// The shadow is staged in chunks of at most ch_cols(TZB) x CH_ROWS pixels, so any
 // geometry works; typical bricks need one chunk.
 #pragma once
 
@@ -26,8 +26,13 @@
 namespace kct {
 
 constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
-constexpr int TZ_DEEP = 24;                // deeper bricks for large volumes (more voxels share a lane's setup)
-constexpr int CH_COLS = 48, CH_ROWS = 40;  // staged shadow chunk
+constexpr int TZ_DEEP = 20;                // deeper bricks for large volumes (more voxels share a lane's setup)
+constexpr int CH_ROWS = 32;                // staged shadow chunk: rows, and columns by brick depth
+// Columns of the staged chunk: 32 for the deep bricks of large volumes (whose
+// shadows are at most about 28 x 28 pixels at typical magnifications; the
+// smaller chunk measured faster there), 48 for the shallow bricks, whose
+// volumes tend to have coarse voxels and wide shadows.
+__host__ __device__ constexpr int ch_cols(int tzb) { return tzb == TZ_DEEP ? 32 : 48; }
 constexpr int NH = 2;                      // detector columns held in registers at once
 
 struct ColStage {  // per staged detector column: in-plane ray parameters
@@ -109,10 +114,10 @@ __host__ __device__ __forceinline__ void column_interval(const ColStage &cs, flo
 
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
 // accumulators of its voxels (ix, iy, iz0 + j), j < nzb, for every staged ray
-// i = (column cu0 + c, row cv0 + r); s_pix[r * CH_COLS + c] describes ray i.
+// i = (column cu0 + c, row cv0 + r); s_pix[r * CHC + c] describes ray i.
 // SQ: accumulate w_ij^2 * le instead of w_ij * le (with le = L^2 this sums the
 // squared weights, the diagonal of A^T A).
-template <typename A, bool SQ = false, int TZN = TZ>
+template <typename A, bool SQ, int CHC, int TZN>
 __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const ViewParam &vp, int ix, int iy, int iz0,
                                                       int nzb, const PixStage<A> *s_pix, const ColStage *s_col,
                                                       int cu0, int ncol, int cv0, int nrow, A (&acc)[TZN])
@@ -188,7 +193,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
                 va = va < cv0 ? cv0 : va;
                 vb = vb > vmax ? vmax : vb;
                 for (int v = va; v <= vb; ++v) {
-                    const PixStage<A> *prow = s_pix + (v - cv0) * CH_COLS + (c0 - cu0);
+                    const PixStage<A> *prow = s_pix + (v - cv0) * CHC + (c0 - cu0);
 #pragma unroll
                     for (int h = 0; h < NH; ++h) {
                         if (h < nh) {
