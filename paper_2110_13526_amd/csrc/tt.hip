@@ -169,14 +169,26 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
             const int ncol = u1 - cu0 + 1 < TT_CH_COLS ? u1 - cu0 + 1 : TT_CH_COLS;
             for (int cv0 = v0; cv0 <= v1; cv0 += TT_CH_ROWS) {
                 const int nrow = v1 - cv0 + 1 < TT_CH_ROWS ? v1 - cv0 + 1 : TT_CH_ROWS;
-                for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
-                    const int r = t / ncol, c = t - r * ncol;
-                    const ColParam cp = ck[cu0 + c];
-                    const RowParam rp = g.rows[cv0 + r];
-                    const A amp = (A)tt_amplitude(ray_length_per_xi(cp.lxy2, rp.qz, cp.gp), cp.inv_a,
-                                                  zeta_inv_slope(rp.inv_qz, cp.kz));
-                    s_le[r * TT_CH_COLS + c] =
-                        SQ ? amp * amp : amp * to_acc(pk[(size_t)(cv0 + r) * g.nu + cu0 + c]);
+                // pixel t = r * ncol + c; t steps by 256: r by dr, c by dc, with carry
+                {
+                    int r = (int)threadIdx.x / ncol, c = (int)threadIdx.x - r * ncol;
+                    const int dr = 256 / ncol, dc = 256 - dr * ncol;
+                    for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
+                        // the projection value first: its load overlaps the parameter loads
+                        // (offsets within one view fit in 32 bits: a projection has < 2^31 rays)
+                        const A ev = SQ ? (A)0 : to_acc(pk[(unsigned)((cv0 + r) * g.nu + cu0 + c)]);
+                        const ColParam cp = ck[cu0 + c];
+                        const RowParam rp = g.rows[cv0 + r];
+                        const A amp = (A)tt_amplitude(ray_length_per_xi(cp.lxy2, rp.qz, cp.gp), cp.inv_a,
+                                                      zeta_inv_slope(rp.inv_qz, cp.kz));
+                        s_le[r * TT_CH_COLS + c] = SQ ? amp * amp : amp * ev;
+                        r += dr;
+                        c += dc;
+                        if (c >= ncol) {
+                            c -= ncol;
+                            ++r;
+                        }
+                    }
                 }
                 __syncthreads();
                 if (valid)
