@@ -175,29 +175,37 @@ __host__ __device__ __forceinline__ void tt_edge_line(const GeoDev &g, const Vie
 }
 
 
-// Sum over the voxels j of ray (iu, iv) of fl(F_u F_v) x_j, without L_i.
-// Walking the view's dominant axis slab by slab, the voxel columns inside the
-// wedge between the rays through the column's two edges are visited (with one
-// cell of margin on each side; columns outside get F_u = 0), and for each, the
-// z-cells whose axial footprint can meet the row.  active = false: the lane
-// takes part in the column's work but adds nothing (a row past the detector).
-// Volume element (iz, iy, ix) is vol_z[(iy nx + ix) nz + iz] (z-fastest copy)
-// or vol[(iz ny + iy) nx + ix].
-template <typename TV>
-__host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const ViewParam &vp, int iu, int iv,
-                                                         bool active, const TV *__restrict__ vol,
-                                                         const TV *__restrict__ vol_z)
+// Sums over the voxels j of rays (iu, iv[r]), r < R, of fl(F_u F_v) x_j,
+// without L_i.  Walking the view's dominant axis slab by slab, the voxel
+// columns inside the wedge between the rays through the column's two edges are
+// visited (with one cell of margin on each side; columns outside get F_u = 0);
+// a column's transaxial footprint is shared by the R rows, and for each row the
+// z-cells whose axial footprint can meet it are visited.  active[r] = false: the
+// lane takes part in the column's work but adds nothing for row r (a row past
+// the detector).  Every row's sum takes its terms in the same order as with
+// R = 1.  Volume element (iz, iy, ix) is vol_z[(iy nx + ix) nz + iz] (z-fastest
+// copy) or vol[(iz ny + iy) nx + ix].
+template <typename TV, int R>
+__host__ __device__ __forceinline__ void tt_ray_sums(const GeoDev &g, const ViewParam &vp, int iu,
+                                                     const int (&iv)[R], const bool (&active)[R],
+                                                     const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+                                                     acc_t<TV> (&acc)[R])
 {
-    acc_t<TV> acc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0;
     const bool dom0 = vp.dom == 0;
     const int nxi = dom0 ? g.nx : g.ny, neta = dom0 ? g.ny : g.nx;
     const float hxi = dom0 ? g.hx : g.hy, heta = dom0 ? g.hy : g.hx;
     float a0, a1, b0, b1;
     tt_edge_line(g, vp, (float)iu - 0.5f, a0, a1);
     tt_edge_line(g, vp, (float)iu + 0.5f, b0, b1);
-    // the row's extent on the detector [mm]; at depth D a ray to height v is at z = v D / SDD
-    const float vlo = ((float)iv - 0.5f - g.cv) * g.dv + g.off_v;
-    const float vhi = ((float)iv + 0.5f - g.cv) * g.dv + g.off_v;
+    // each row's extent on the detector [mm]; at depth D a ray to height v is at z = v D / SDD
+    float vlo[R], vhi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        vlo[r] = ((float)iv[r] - 0.5f - g.cv) * g.dv + g.off_v;
+        vhi[r] = ((float)iv[r] + 0.5f - g.cv) * g.dv + g.off_v;
+    }
     const float rsdd = 1.0f / g.sdd;
     const float roff = tt_row_offset(g);
     for (int m = 0; m < nxi; ++m) {
@@ -213,28 +221,31 @@ __host__ __device__ __forceinline__ acc_t<TV> tt_ray_sum(const GeoDev &g, const 
             float dmin, dmax, rdmin, rdmax;
             tt_transaxial(g, vp, ix, iy, tu, dmin, dmax, rdmin, rdmax);
             const float fu = tt_mean(tu, iu);
-            if (!(fu > 0.0f) || !active) continue;
+            if (!(fu > 0.0f)) continue;
             float ka, kb;
             tt_row_scales(g, rdmin, rdmax, ka, kb);
-            const float z1 = vlo * dmin * rsdd, z2 = vlo * dmax * rsdd;
-            const float z3 = vhi * dmin * rsdd, z4 = vhi * dmax * rsdd;
-            const float zmn = fminf(fminf(z1, z2), fminf(z3, z4)), zmx = fmaxf(fmaxf(z1, z2), fmaxf(z3, z4));
-            int za = (int)floorf((zmn - g.z0) * g.inv_vz) - 1, zb = (int)floorf((zmx - g.z0) * g.inv_vz) + 1;
-            za = za < 0 ? 0 : za;
-            zb = zb > g.nz - 1 ? g.nz - 1 : zb;
-            for (int iz = za; iz <= zb; ++iz) {
-                TTTrap tv;
-                tt_axial(g, iz, ka, kb, roff, tv);
-                const float fv = tt_mean(tv, iv);
-                if (fv > 0.0f) {
-                    const TV xv = vol_z ? vol_z[((size_t)iy * g.nx + ix) * g.nz + iz]
-                                        : vol[((size_t)iz * g.ny + iy) * g.nx + ix];
-                    acc = fma_acc(fu * fv, to_acc(xv), acc);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (!active[r]) continue;
+                const float z1 = vlo[r] * dmin * rsdd, z2 = vlo[r] * dmax * rsdd;
+                const float z3 = vhi[r] * dmin * rsdd, z4 = vhi[r] * dmax * rsdd;
+                const float zmn = fminf(fminf(z1, z2), fminf(z3, z4)), zmx = fmaxf(fmaxf(z1, z2), fmaxf(z3, z4));
+                int za = (int)floorf((zmn - g.z0) * g.inv_vz) - 1, zb = (int)floorf((zmx - g.z0) * g.inv_vz) + 1;
+                za = za < 0 ? 0 : za;
+                zb = zb > g.nz - 1 ? g.nz - 1 : zb;
+                for (int iz = za; iz <= zb; ++iz) {
+                    TTTrap tv;
+                    tt_axial(g, iz, ka, kb, roff, tv);
+                    const float fv = tt_mean(tv, iv[r]);
+                    if (fv > 0.0f) {
+                        const TV xv = vol_z ? vol_z[((size_t)iy * g.nx + ix) * g.nz + iz]
+                                            : vol[((size_t)iz * g.ny + iy) * g.nx + ix];
+                        acc[r] = fma_acc(fu * fv, to_acc(xv), acc[r]);
+                    }
                 }
             }
         }
     }
-    return acc;
 }
 
 // One lane's share of one staged chunk: add fl(F_u F_v) * s_le[pixel] to acc[j]

@@ -26,6 +26,7 @@
 namespace kct {
 
 constexpr int TT_COLS = 4;                           // forward: detector columns per workgroup
+constexpr int TT_R = 2;                              // forward: detector rows per lane (share a column's footprints)
 constexpr int TT_CH_COLS = 48, TT_CH_ROWS = 40;      // backward: staged shadow chunk
 constexpr int TT_NXCD = 8;
 constexpr int TT_TZ = TZ;                            // backward: voxels per lane along z
@@ -39,7 +40,7 @@ __host__ __device__ __forceinline__ TTFwdGrid tt_fwd_grid(const GeoDev &g)
 {
     TTFwdGrid f;
     f.ncg = (g.nu + TT_COLS - 1) / TT_COLS;
-    f.nbands = (g.nv + 63) / 64;
+    f.nbands = (g.nv + 64 * TT_R - 1) / (64 * TT_R);
     f.nviews = g.nviews;
     f.nblocks = (int64_t)f.ncg * f.nbands * f.nviews;
     return f;
@@ -84,19 +85,28 @@ __global__ __launch_bounds__(256) void k_forward_tt(GeoDev g, const TV *__restri
     const int k = (int)(rest % fg.nviews);
     const int band = (int)(rest / fg.nviews);
     const int iu = cg * TT_COLS + (int)(threadIdx.x >> 6);
-    const int iv = band * 64 + (int)(threadIdx.x & 63);
     const bool col_ok = iu < g.nu;
-    const bool ok = col_ok && iv < g.nv;
-    A acc = 0;
-    if (col_ok) acc = tt_ray_sum<TV>(g, g.views[k], iu, iv, ok, vol, vol_z);
+    // lane rows: band * 64 TT_R + lane + 64 r
+    int iv[TT_R];
+    bool ok[TT_R];
+#pragma unroll
+    for (int r = 0; r < TT_R; ++r) {
+        iv[r] = band * 64 * TT_R + (int)(threadIdx.x & 63) + 64 * r;
+        ok[r] = col_ok && iv[r] < g.nv;
+    }
+    A acc[TT_R] = {};
+    if (col_ok) tt_ray_sums<TV, TT_R>(g, g.views[k], iu, iv, ok, vol, vol_z, acc);
     double sq = 0.0;
-    if (ok) {
-        const ColParam cp = g.cols[(size_t)k * g.nu + iu];
-        const RowParam rp = g.rows[iv];
-        const float amp = tt_amplitude(ray_length_per_xi(cp.lxy2, rp.qz, cp.gp), cp.inv_a,
-                                       zeta_inv_slope(rp.inv_qz, cp.kz));
-        const size_t ray = ((size_t)k * g.nv + iv) * g.nu + iu;
-        sq = fwd_store<TP, EPI, A>(out, aux, sc, ray, (A)amp * acc);
+#pragma unroll
+    for (int r = 0; r < TT_R; ++r) {
+        if (ok[r]) {
+            const ColParam cp = g.cols[(size_t)k * g.nu + iu];
+            const RowParam rp = g.rows[iv[r]];
+            const float amp = tt_amplitude(ray_length_per_xi(cp.lxy2, rp.qz, cp.gp), cp.inv_a,
+                                           zeta_inv_slope(rp.inv_qz, cp.kz));
+            const size_t ray = ((size_t)k * g.nv + iv[r]) * g.nu + iu;
+            sq += fwd_store<TP, EPI, A>(out, aux, sc, ray, (A)amp * acc[r]);
+        }
     }
     if (EPI != FWD_PLAIN) {
         const double bs = tt_block_sum(sq);
