@@ -178,7 +178,7 @@ __host__ __device__ __forceinline__ void tt_edge_line(const GeoDev &g, const Vie
 // Sums over the voxels j of rays (iu, iv[r]), r < R, of fl(F_u F_v) x_j,
 // without L_i.  Walking the view's dominant axis slab by slab, the voxel
 // columns inside the wedge between the rays through the column's two edges are
-// visited (with one cell of margin on each side; columns outside get F_u = 0);
+// visited (widened by 0.01 cell against rounding; columns outside get F_u = 0);
 // a column's transaxial footprint is shared by the R rows, and for each row the
 // z-cells whose axial footprint can meet it are visited.  active[r] = false: the
 // lane takes part in the column's work but adds nothing for row r (a row past
@@ -212,7 +212,9 @@ __host__ __device__ __forceinline__ void tt_ray_sums(const GeoDev &g, const View
         const float xl = (float)m - hxi, xh = xl + 1.0f;
         const float ea = a0 + a1 * xl, eb = a0 + a1 * xh, ec = b0 + b1 * xl, ed = b0 + b1 * xh;
         const float emin = fminf(fminf(ea, eb), fminf(ec, ed)), emax = fmaxf(fmaxf(ea, eb), fmaxf(ec, ed));
-        int e_lo = (int)floorf(emin + heta) - 1, e_hi = (int)floorf(emax + heta) + 1;
+        // the eta-cells meeting [emin, emax], widened by 0.01 cell against the rounding
+        // differences to tt_transaxial's breakpoints
+        int e_lo = (int)floorf(emin + heta - 0.01f), e_hi = (int)floorf(emax + heta + 0.01f);
         e_lo = e_lo < 0 ? 0 : e_lo;
         e_hi = e_hi > neta - 1 ? neta - 1 : e_hi;
         for (int e = e_lo; e <= e_hi; ++e) {
@@ -230,7 +232,9 @@ __host__ __device__ __forceinline__ void tt_ray_sums(const GeoDev &g, const View
                 const float z1 = vlo[r] * dmin * rsdd, z2 = vlo[r] * dmax * rsdd;
                 const float z3 = vhi[r] * dmin * rsdd, z4 = vhi[r] * dmax * rsdd;
                 const float zmn = fminf(fminf(z1, z2), fminf(z3, z4)), zmx = fmaxf(fmaxf(z1, z2), fmaxf(z3, z4));
-                int za = (int)floorf((zmn - g.z0) * g.inv_vz) - 1, zb = (int)floorf((zmx - g.z0) * g.inv_vz) + 1;
+                // the z-cells meeting [zmn, zmx], widened by 0.01 cell against the rounding
+                // differences to tt_axial's breakpoints (relative ~1e-6 of z)
+                int za = (int)floorf((zmn - g.z0) * g.inv_vz - 0.01f), zb = (int)floorf((zmx - g.z0) * g.inv_vz + 0.01f);
                 za = za < 0 ? 0 : za;
                 zb = zb > g.nz - 1 ? g.nz - 1 : zb;
                 for (int iz = za; iz <= zb; ++iz) {
