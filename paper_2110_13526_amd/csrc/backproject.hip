@@ -88,8 +88,11 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 vmin = fminf(vmin, __shfl_xor(vmin, off, 8));
                 vmax = fmaxf(vmax, __shfl_xor(vmax, off, 8));
             }
-            const int a0 = (int)floorf(umin) - 1, a1 = (int)ceilf(umax) + 1;
-            const int b0 = (int)floorf(vmin) - 1, b1 = (int)ceilf(vmax) + 1;
+            // a ray through the brick meets the detector inside the convex hull of the
+            // projected corners: the pixel centres in [min, max], widened by 0.01 pixel
+            // against rounding (relative ~1e-7 of the coordinates)
+            const int a0 = (int)ceilf(umin - 0.01f), a1 = (int)floorf(umax + 0.01f);
+            const int b0 = (int)ceilf(vmin - 0.01f), b1 = (int)floorf(vmax + 0.01f);
             u0 = __builtin_amdgcn_readfirstlane(a0 < 0 ? 0 : a0);
             u1 = __builtin_amdgcn_readfirstlane(a1 > g.nu - 1 ? g.nu - 1 : a1);
             v0 = __builtin_amdgcn_readfirstlane(b0 < 0 ? 0 : b0);
