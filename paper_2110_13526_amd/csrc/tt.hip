@@ -163,8 +163,10 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
                 vmin = fminf(vmin, __shfl_xor(vmin, off, 8));
                 vmax = fmaxf(vmax, __shfl_xor(vmax, off, 8));
             }
-            const int a0 = (int)floorf(umin) - 1, a1 = (int)ceilf(umax) + 1;
-            const int b0 = (int)floorf(vmin) - 1, b1 = (int)ceilf(vmax) + 1;
+            // a pixel meets a footprint inside the projected corners' hull when its
+            // extent (centre +- 0.5) overlaps the hull; 0.01 pixel more against rounding
+            const int a0 = (int)ceilf(umin - 0.51f), a1 = (int)floorf(umax + 0.51f);
+            const int b0 = (int)ceilf(vmin - 0.51f), b1 = (int)floorf(vmax + 0.51f);
             u0 = __builtin_amdgcn_readfirstlane(a0 < 0 ? 0 : a0);
             u1 = __builtin_amdgcn_readfirstlane(a1 > g.nu - 1 ? g.nu - 1 : a1);
             v0 = __builtin_amdgcn_readfirstlane(b0 < 0 ? 0 : b0);
