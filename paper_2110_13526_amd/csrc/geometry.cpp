@@ -32,6 +32,15 @@ std::string validate_geometry(const kct_volume_desc &v, const kct_cone_desc &c)
     return "";
 }
 
+// Offset h of an axis' index frame (plane m at m - h): the multiple of 1/2 in
+// [0, n] nearest to the index of coordinate 0, where the lower corner is at lo
+// and cells are v wide.  Exactly n/2 when the axis is centred on 0.
+static double plane_offset(double lo, double v, int n)
+{
+    double h = std::round(-2.0 * lo / v) * 0.5;
+    return h < 0.0 ? 0.0 : (h > (double)n ? (double)n : h);
+}
+
 static double view_angle(const kct_cone_desc &c, int k)
 {
     if (c.angles) return c.angles[k];
@@ -61,6 +70,16 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
     const double X0 = vol.cx - 0.5 * vol.nx * vol.vx, Y0 = vol.cy - 0.5 * vol.ny * vol.vy;
     const double Z0 = vol.cz - 0.5 * vol.nz * vol.vz;
     const double X1 = X0 + vol.nx * vol.vx, Y1 = Y0 + vol.ny * vol.vy, Z1 = Z0 + vol.nz * vol.vz;
+    // Index frame of each axis: plane m sits at m - h, h the multiple of 1/2 in
+    // [0, n] nearest to the isocentre's index (n/2 for a centred volume).  A
+    // ray nearly parallel to an axis' planes has a crossing that moves by
+    // (coordinate error) / slope; such rays pass near the isocentre, where
+    // coordinates measured from it are small and carry small rounding errors.
+    const double hx = plane_offset(X0, vol.vx, vol.nx), hy = plane_offset(Y0, vol.vy, vol.ny);
+    const double hz = plane_offset(Z0, vol.vz, vol.nz);
+    // world coordinates of each frame's origin (the volume centre when centred)
+    const double ox = vol.cx + (hx - 0.5 * vol.nx) * vol.vx, oy = vol.cy + (hy - 0.5 * vol.ny) * vol.vy;
+    const double oz = vol.cz + (hz - 0.5 * vol.nz) * vol.vz;
 
     for (int iv = 0; iv < nv; ++iv) {
         double qz = ((double)iv - 0.5 * (nv - 1)) * cone.dv + cone.off_v;
@@ -95,7 +114,7 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
         vp.dom = dom;
         vp.pad[0] = vp.pad[1] = vp.pad[2] = 0;
         const double vxi = dom == 0 ? vol.vx : vol.vy, veta = dom == 0 ? vol.vy : vol.vx;
-        const double cxi = dom == 0 ? vol.cx : vol.cy, ceta = dom == 0 ? vol.cy : vol.cx;
+        const double cxi = dom == 0 ? ox : oy, ceta = dom == 0 ? oy : ox;
         const double Sxi = dom == 0 ? Sx : Sy, Seta = dom == 0 ? Sy : Sx;
         for (int iu = 0; iu < nu; ++iu) {
             const double u = ((double)iu - 0.5 * (nu - 1)) * cone.du + cone.off_u;
@@ -136,10 +155,10 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
     d.x0 = (float)X0;
     d.y0 = (float)Y0;
     d.z0 = (float)Z0;
-    d.hx = 0.5f * (float)vol.nx;
-    d.hy = 0.5f * (float)vol.ny;
-    d.hz = 0.5f * (float)vol.nz;
-    d.zc = (float)(vol.cz / vol.vz);
+    d.hx = (float)hx;
+    d.hy = (float)hy;
+    d.hz = (float)hz;
+    d.zc = (float)(oz / vol.vz);
     d.inv_vz = (float)(1.0 / vol.vz);
     d.sdd = (float)cone.sdd;
     d.du = (float)cone.du;

@@ -143,7 +143,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
             hb = iu;
         }
     }
-    const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (centred index)
+    const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (index frame)
     const float zz0 = mbz0 + g.zc;         // the same plane as a height above the source plane
     const float vofs = -g.off_v * g.inv_dv + g.cv;
     const float vofs_lo = vofs - 0.01f, vofs_hi = vofs + 0.01f;

@@ -10,16 +10,22 @@
 //
 // Ray parametrisation.  For each view one in-plane axis is "dominant" (x when
 // |cos t| / vx >= |sin t| / vy, else y); call it xi and the other in-plane axis
-// eta.  Coordinates are voxel-index units centred on the volume centre, so the
-// voxel planes along an axis with n cells sit at m - n/2, m = 0..n.  A ray of
-// detector column iu and row iv is then
+// eta.  Coordinates are voxel-index units: along an axis with n cells plane m
+// (m = 0..n) sits at m - h, where the plane offset h is the multiple of 1/2 in
+// [0, n] nearest to the isocentre's index (h = n/2 for a volume centred on the
+// isocentre, so the origin is the volume centre).  A ray of detector column iu
+// and row iv is then
 //     eta(xi)  = eta_c + a * xi                       (column parameters)
 //     zeta(xi) = zeta_c + xi / czr,  zeta_c = qz * tcv - zc,  czr = inv_qz * kz
 // and its length in mm per unit of xi is L = sqrt(lxy2 + (qz * gp)^2).
-// The ray crosses eta-plane mb (centred) at xi = (mb - eta_c) * inv_a and
-// zeta-plane mb at xi = (mb - zeta_c) * czr.  Parametrising by the centred
+// The ray crosses eta-plane mb (index frame) at xi = (mb - eta_c) * inv_a and
+// zeta-plane mb at xi = (mb - zeta_c) * czr.  Parametrising by the voxel
 // index along the dominant axis keeps every quantity O(volume size), so single
-// precision resolves a crossing to about 1e-5 of a voxel.
+// precision resolves a crossing to about 1e-5 of a voxel.  Rays nearly
+// parallel to an axis' planes (the most sensitive crossings: an error in the
+// coordinate moves the crossing by error / slope) pass near the isocentre; with
+// the origin there their coordinates are small and so are their roundings,
+// also for off-centre volumes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -30,7 +36,7 @@
 namespace kct {
 
 struct ColParam {    // per (view, detector column)
-    float eta_c;     // eta (centred index) where the ray meets the plane xi = 0
+    float eta_c;     // eta (index frame) where the ray meets the plane xi = 0
     float inv_a;     // d xi / d eta; 0 when the ray is parallel to the eta planes
     float a;         // d eta / d xi
     float tcv;       // (fraction of the source->pixel segment at xi = 0) / vz
@@ -57,8 +63,8 @@ struct GeoDev {
     int nx, ny, nz, nviews, nu, nv;
     float vx, vy, vz;
     float x0, y0, z0;        // world coordinates of the volume's lower corner [mm]
-    float hx, hy, hz;        // nx/2, ny/2, nz/2
-    float zc;                // cz / vz
+    float hx, hy, hz;        // plane offsets: plane m of an axis at m - h (n/2 when centred)
+    float zc;                // z / vz of the zeta frame's origin (0 when centred)
     float inv_vz;
     float sdd, du, dv, off_u, off_v;
     float inv_du, inv_dv;

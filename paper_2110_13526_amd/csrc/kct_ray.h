@@ -14,7 +14,7 @@ namespace kct {
 
 // z-walk state of one ray: current z-cell mz (-1 / nz stand for "below" /
 // "above" the volume), walking direction stz (and as a float, fstz), the
-// centred coordinate hbf of the plane where the walk leaves mz (an exact small
+// index-frame coordinate hbf of the plane where the walk leaves mz (an exact small
 // integer or half-integer, so stepping it by +-1 is exact), and the crossings lz
 // (entry into mz) and hzv (exit from mz; +inf once the walk has left the
 // volume's planes).
@@ -43,7 +43,7 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
         if (s.mz < 0 || s.mz >= nz) { s.mz = -1; s.lz = INFINITY; }
         return;
     }
-    const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at(hz, zeta_c, czr);
+    const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at((float)nz - hz, zeta_c, czr);
     if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) {
         s.mz = -1;
         s.stz = 0;
@@ -86,7 +86,7 @@ __host__ __device__ __forceinline__ void zwalk_steps(ZWalk &s, const T *__restri
         s.lz = s.hzv;
         s.mz += s.stz;
         s.hbf += s.fstz;
-        s.hzv = fabsf(s.hbf) <= hz ? cross_at(s.hbf, s.zeta_c, s.czr) : INFINITY;
+        s.hzv = (s.hbf >= -hz && s.hbf <= (float)nz - hz) ? cross_at(s.hbf, s.zeta_c, s.czr) : INFINITY;
         zwalk_eval<T, SZ>(s, col, sz, nz, t0, t1, acc);
     }
 }
@@ -127,13 +127,14 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
         lo_e = in ? -INFINITY : INFINITY;
         hi_e = in ? INFINITY : -INFINITY;
     } else {
-        const float b0 = cross_at(-heta, eta_c, inv_a), b1 = cross_at(heta, eta_c, inv_a);
+        const float b0 = cross_at(-heta, eta_c, inv_a), b1 = cross_at((float)neta - heta, eta_c, inv_a);
         lo_e = fminf(b0, b1);
         hi_e = fmaxf(b0, b1);
     }
     const float t_start = fmaxf(-hxi, lo_e);
-    const float t_end = fminf(hxi, hi_e);
+    const float t_end = fminf((float)nxi - hxi, hi_e);
     if (!(t_end > t_start)) return;
+    const float zhi = (float)nz - hz;  // the top z-plane
     ZWalk zs[R];
     bool any = false;
 #pragma unroll
@@ -209,7 +210,7 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
             ZWalk &z = zs[r];
             const bool c = z.hzv < t1;
             const float nhbf = z.hbf + z.fstz;
-            const float nhzv = fabsf(nhbf) <= hz ? cross_at(nhbf, z.zeta_c, z.czr) : INFINITY;
+            const float nhzv = (nhbf >= -hz && nhbf <= zhi) ? cross_at(nhbf, z.zeta_c, z.czr) : INFINITY;
             if (c) {
                 z.lz = z.hzv;
                 z.mz += z.stz;

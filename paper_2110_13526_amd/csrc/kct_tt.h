@@ -160,7 +160,7 @@ __host__ __device__ __forceinline__ void tt_pixels(float t0, float t3, int &a, i
 }
 
 // In-plane line through the source and the detector point at column coordinate
-// uc, in the view's dominant frame of centred voxel indices: eta = e0 + e1 xi.
+// uc, in the view's dominant frame of voxel indices (kct_internal.h): eta = e0 + e1 xi.
 __host__ __device__ __forceinline__ void tt_edge_line(const GeoDev &g, const ViewParam &vp, float uc, float &e0, float &e1)
 {
     const float umm = (uc - g.cu) * g.du + g.off_u;

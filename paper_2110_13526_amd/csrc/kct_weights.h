@@ -14,8 +14,9 @@
 // ray's sum by it, the backprojector multiplies the projection value by it.
 //
 // A ray parallel to the planes of an axis (a = 0 or qz = 0) is inside the one
-// cell floor(c + n/2) of that axis (cells are half-open [lo, hi)), over the
-// whole xi range.
+// cell floor(c + h) of that axis (cells are half-open [lo, hi); plane m of the
+// axis is at m - h in its index frame, see kct_internal.h), over the whole xi
+// range.
 //
 // Floating-point contraction is switched off here: fused multiply-adds could
 // otherwise round the same expression differently in the two kernels.
@@ -30,12 +31,15 @@
 
 namespace kct {
 
-// xi at which the ray crosses the plane mb (centred index) of an axis whose
+// xi at which the ray crosses the plane mb (index frame) of an axis whose
 // coordinate along the ray is c + xi / inv.
 __host__ __device__ __forceinline__ float cross_at(float mb, float c, float inv) { return (mb - c) * inv; }
 
-// zeta of the ray at xi = 0, and d xi / d zeta.
-__host__ __device__ __forceinline__ float zeta_centre(float qz, float tcv, float zc) { return qz * tcv - zc; }
+// zeta of the ray at xi = 0 (one rounding), and d xi / d zeta.
+__host__ __device__ __forceinline__ float zeta_centre(float qz, float tcv, float zc)
+{
+    return __builtin_fmaf(qz, tcv, -zc);
+}
 __host__ __device__ __forceinline__ float zeta_inv_slope(float inv_qz, float kz) { return inv_qz * kz; }
 
 // Length of the ray in mm per unit of xi.  On the GPU the hardware square root
@@ -51,13 +55,15 @@ __host__ __device__ __forceinline__ float ray_length_per_xi(float lxy2, float qz
 #endif
 }
 
-// The cell (0-based) that a ray parallel to an axis' planes lies in.
-__host__ __device__ __forceinline__ int parallel_cell(float c, float half_n) { return (int)floorf(c + half_n); }
+// The cell (0-based) that a ray parallel to an axis' planes lies in (h: the
+// axis' plane offset).
+__host__ __device__ __forceinline__ int parallel_cell(float c, float h) { return (int)floorf(c + h); }
 
-// xi-range [lo, hi] of cell m of an axis with n cells (half_n = n/2), for a ray
-// whose coordinate on that axis is c + xi / inv (inv == 0: parallel).  mb must
-// be the cell's lower plane, (float)m - half_n (exact), passed in so callers
-// that walk consecutive cells need not recompute it.
+// xi-range [lo, hi] of cell m of an axis with plane offset half_n (plane m at
+// m - half_n), for a ray whose coordinate on that axis is c + xi / inv (inv ==
+// 0: parallel).  mb must be the cell's lower plane, (float)m - half_n (exact:
+// half_n is a multiple of 1/2), passed in so callers that walk consecutive
+// cells need not recompute it.
 __host__ __device__ __forceinline__ void cell_range_mb(int m, float mb, float half_n, float c, float inv, float &lo,
                                                        float &hi)
 {
