@@ -78,6 +78,9 @@ def lib():
         L.oracle_diag_normal.restype = None
         L.oracle_cgls_jacobi.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
         L.oracle_cgls_jacobi.restype = ctypes.c_int
+        L.oracle_cgls_jacobi_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                                  dp, dp, dp, ip]
+        L.oracle_cgls_jacobi_ex.restype = ctypes.c_int
         L.oracle_tt_project.argtypes = geo + [dp, dp]
         L.oracle_tt_project.restype = None
         L.oracle_tt_backproject.argtypes = geo + [dp, dp]
@@ -236,16 +239,18 @@ def diag_normal(g):
     return out.reshape(g.nz, g.ny, g.nx)
 
 
-def cgls_jacobi(g, b, K, x0=None, err=0.0):
-    """Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)) in FP64."""
+def cgls_jacobi(g, b, K, x0=None, err=0.0, projector="siddon"):
+    """Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)) in FP64,
+    with the Siddon or the TT operator and that operator's diagonal."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
     hist = np.zeros(max(K, 1), dtype=np.float64)
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
-    stop = lib().oracle_cgls_jacobi(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                                    _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
+    stop = lib().oracle_cgls_jacobi_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
+                                       PROJECTORS[projector], _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0),
+                                       ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 

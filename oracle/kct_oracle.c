@@ -637,15 +637,18 @@ done:
     return stop;
 }
 
+void oracle_tt_diag_normal(const int32_t *dims, const double *par, const double *angles, double *out);
+
 /*
  * Jacobi-preconditioned CGLS (Section 5): Algorithm 1 applied to the operator
  * A M, M = diag(A^T A)^(-1/2) (0 where the diagonal is 0), for the correction
  * z of x = x0 + M z, starting from z = 0.  Products: (A M) d = A (M d),
- * (A M)^T e = M (A^T e).  NB = |b - A x| as in Algorithm 1.
+ * (A M)^T e = M (A^T e).  NB = |b - A x| as in Algorithm 1.  projector 0 is the
+ * Siddon pair, 1 the TT pair (Sections 3, 4) with its own diagonal.
  */
-int oracle_cgls_jacobi(const int32_t *dims, const double *par, const double *angles,
-                       const double *b, double *x, int K, double err, int x0_is_zero, double *history,
-                       double *out_nb, double *out_nb0, int *out_iters)
+int oracle_cgls_jacobi_ex(const int32_t *dims, const double *par, const double *angles,
+                          const double *b, double *x, int K, double err, int x0_is_zero, int projector,
+                          double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
     og_t g = og_make(dims, par, angles);
     int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -659,18 +662,19 @@ int oracle_cgls_jacobi(const int32_t *dims, const double *par, const double *ang
     int stop = OG_STOP_MAXITER, i = 0;
     double NB0 = sqrt(og_dot(b, b, m)), NB = NB0;
     if (K <= 0) goto done;
-    oracle_diag_normal(dims, par, angles, M);
+    if (projector == 1) oracle_tt_diag_normal(dims, par, angles, M);
+    else oracle_diag_normal(dims, par, angles, M);
     for (int64_t t = 0; t < n; ++t) M[t] = M[t] > 0.0 ? 1.0 / sqrt(M[t]) : 0.0;
     if (x0_is_zero) memset(x, 0, sizeof(double) * (size_t)n);
     /* e = b - A x0 */
     if (x0_is_zero) memset(p, 0, sizeof(double) * (size_t)m);
-    else oracle_project(dims, par, angles, x, p);
+    else og_A(projector, dims, par, angles, x, p);
     for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
     NB = sqrt(og_dot(e, e, m));
     double NR2_old = 0.0;
     while (i < K) {
         /* r = (A M)^T e */
-        oracle_backproject(dims, par, angles, e, r);
+        og_AT(projector, dims, par, angles, e, r);
         for (int64_t t = 0; t < n; ++t) r[t] *= M[t];
         double NR2 = og_dot(r, r, n);
         if (NR2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
@@ -682,7 +686,7 @@ int oracle_cgls_jacobi(const int32_t *dims, const double *par, const double *ang
         NR2_old = NR2;
         /* p = (A M) d; alpha = NR2 / |p|^2; z += alpha d, i.e. x += alpha M d; e -= alpha p */
         for (int64_t t = 0; t < n; ++t) md[t] = M[t] * d[t];
-        oracle_project(dims, par, angles, md, p);
+        og_A(projector, dims, par, angles, md, p);
         double NP2 = og_dot(p, p, m);
         if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         double alpha = NR2 / NP2;
@@ -701,6 +705,14 @@ done:
     if (out_iters) *out_iters = i;
     free(M); free(d); free(r); free(md); free(e); free(p);
     return stop;
+}
+
+int oracle_cgls_jacobi(const int32_t *dims, const double *par, const double *angles,
+                       const double *b, double *x, int K, double err, int x0_is_zero, double *history,
+                       double *out_nb, double *out_nb0, int *out_iters)
+{
+    return oracle_cgls_jacobi_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0, history, out_nb, out_nb0,
+                                 out_iters);
 }
 
 int oracle_cgls(const int32_t *dims, const double *par, const double *angles,

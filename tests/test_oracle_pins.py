@@ -390,6 +390,35 @@ def test_jacobi_cgls_is_preconditioned_krylov_minimiser(small_problem, K):
     assert rel(oracle.cgls_jacobi(g, b, K).x.ravel(), M * z) < 1e-8
 
 
+def _tt_matrix(g):
+    """The TT matrix, column by column: the TT oracle's projection of every unit vector."""
+    cols = []
+    e = np.zeros(g.n_vox)
+    for j in range(g.n_vox):
+        e[j] = 1.0
+        cols.append(sp.csc_matrix(oracle.tt_project(g, e.reshape(g.vol_shape)).reshape(-1, 1)))
+        e[j] = 0.0
+    return sp.hstack(cols).tocsr()
+
+
+@pytest.mark.parametrize("K", [1, 3, 6])
+def test_tt_jacobi_cgls_is_preconditioned_krylov_minimiser(small_problem, K):
+    """Jacobi CGLS on the TT operator (Section 5's preconditioner with the
+    projector of Section 4): the iterate minimises |b - A_TT x| over
+    x0 + M span{r0, (M A^T A M) r0, ...} with M = diag(A_TT^T A_TT)^(-1/2) taken
+    from the explicitly formed TT matrix."""
+    g, _, b = small_problem
+    A = _tt_matrix(g)
+    dg = np.asarray(A.multiply(A).sum(axis=0)).ravel()
+    assert rel(oracle.tt_diag_normal(g).ravel(), dg) < 1e-12
+    M = np.where(dg > 0, 1.0 / np.sqrt(np.where(dg > 0, dg, 1.0)), 0.0)
+    x0 = ki.random_volume(g, 36).ravel() * 0.05
+    got = oracle.cgls_jacobi(g, b, K, x0=x0, projector="tt").x.ravel()
+    assert rel(got, krylov_minimiser_jacobi(A, b.ravel(), x0, K, M)) < 1e-9
+    z = spla.lsqr(A @ sp.diags(M), b.ravel(), atol=0.0, btol=0.0, conlim=0.0, iter_lim=K)[0]
+    assert rel(oracle.cgls_jacobi(g, b, K, projector="tt").x.ravel(), M * z) < 1e-8
+
+
 def test_tikhonov_cgls_with_initial_guess(small_problem):
     """With x0 the Tikhonov CGLS is CGLS on the stacked system [A; lambda I] x = [b; 0]
     started at x0: scipy's LSQR on the explicitly stacked matrix gives the same iterate."""
@@ -505,3 +534,23 @@ def test_tt_approaches_siddon_with_resolution():
         bt, bs = oracle.tt_project(g, x), oracle.project(g, x)
         diffs.append(rel(bt, bs))
     assert diffs[0] > diffs[1] > diffs[2] and diffs[2] < 0.025, diffs
+
+
+@pytest.mark.parametrize("variant", ["base", "offcenter", "aniso", "odd"])
+def test_tt_diag_normal_is_squared_column_norms(variant):
+    """diag(A_TT^T A_TT)_j = sum_i a_ij^2 (Section 5's Jacobi diagonal for the
+    TT projector), against the squared norms of the columns of A_TT formed one
+    by one as the TT projection of every unit vector e_j (the matrix entries
+    themselves are pinned by the quadrature test above)."""
+    g = ki.t16(variant)
+    ref = np.empty(g.n_vox)
+    e = np.zeros(g.n_vox)
+    for j in range(g.n_vox):
+        e[j] = 1.0
+        col = oracle.tt_project(g, e.reshape(g.vol_shape)).ravel()
+        ref[j] = col @ col
+        e[j] = 0.0
+    got = oracle.tt_diag_normal(g).ravel()
+    assert ref.min() >= 0 and ref.max() > 0
+    assert np.abs(got - ref).max() <= 1e-12 * ref.max()
+    assert rel(got, ref) < 1e-12
