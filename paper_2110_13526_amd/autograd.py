@@ -89,7 +89,11 @@ def backproject_fn(g, y):
 
 
 def _sq(t):
-    """|t|^2 per batch item, keeping dimensions for broadcasting."""
+    """|t|^2 per batch item in double precision, keeping dimensions for
+    broadcasting.  CGLS's scalars (NR2, |p|^2, alpha, beta) are formed in
+    double precision whatever the vectors' type, like the library's solver;
+    only the vector updates use the vectors' type."""
+    t = t.double()
     return (t * t).sum(dim=(-3, -2, -1), keepdim=True)
 
 
@@ -105,11 +109,11 @@ def _iteration(g, x, r, d, e, nr2_old, first: bool, last: bool):
     if first:
         d = r
     else:
-        d = r + (nr2 / nr2_old) * d
+        d = r + (nr2 / nr2_old).to(r.dtype) * d
     p = project_fn(g, d)
     alpha = nr2 / _sq(p)
-    x = x + alpha * d
-    e = e - alpha * p
+    x = x + alpha.to(x.dtype) * d
+    e = e - alpha.to(e.dtype) * p
     if not last:
         r = backproject_fn(g, e)
     return x, r, d, e, nr2
@@ -118,7 +122,8 @@ def _iteration(g, x, r, d, e, nr2_old, first: bool, last: bool):
 def cgls_unrolled(g, b, K: int, checkpoint: bool = True):
     """K CGLS iterations (Algorithm 1, x0 = 0, no early stop) differentiable in b.
 
-    b: (..., n_views, nv, nu), float32 or float64.  Returns x_K with b's dtype.
+    b: (..., n_views, nv, nu), float32 or float64.  Returns x_K with b's dtype;
+    the scalars of every iteration are double precision.
     Iterations that would divide by zero (b = 0) are the caller's concern: the
     differentiable form has no breakdown test."""
     if K < 1:
@@ -128,7 +133,7 @@ def cgls_unrolled(g, b, K: int, checkpoint: bool = True):
     e = b
     r = backproject_fn(g, e)
     d = torch.zeros_like(x)
-    nr2 = torch.ones(lead + (1, 1, 1), dtype=b.dtype, device=b.device)
+    nr2 = torch.ones(lead + (1, 1, 1), dtype=torch.float64, device=b.device)
     for it in range(K):
         first, last = it == 0, it == K - 1
         if checkpoint:
