@@ -383,11 +383,14 @@ __global__ __launch_bounds__(TB) void kb_vec(const BatchInst *__restrict__ B, in
         if (threadIdx.x == 0) bi->part[lb] = bs;
         return;
     }
-    if (sc->done) return;
-    if (op == BV_X0_E) {  // x0 = 0, e = b
+    if (op == BV_X0_E) {  // x0 = 0 (also when the solve stopped at once: K = 0 or b = 0), e = b
         for (int64_t k = i0; k < bi->n; k += stride) bi->x[k] = 0.0f;
+        if (sc->done) return;
         for (int64_t k = i0; k < bi->m; k += stride) bi->e[k] = bi->b[k];
-    } else if (op == BV_CGLS_X) {  // x += alpha d
+        return;
+    }
+    if (sc->done) return;
+    if (op == BV_CGLS_X) {  // x += alpha d
         const float alpha = (float)sc->x_alpha;
         for (int64_t k = i0; k < bi->n; k += stride) bi->x[k] = bi->x[k] + alpha * bi->d[k];
     } else if (op == BV_CGLS_E) {  // e -= alpha p, partials of |e|^2

@@ -97,6 +97,21 @@ def test_batch_tuner_and_cache(small_batch, tmp_path):
     batch2.close()
 
 
+def test_batch_zero_iterations_returns_zeros(small_batch):
+    """K = 0 returns x0 = 0 in every instance (the iterate is written even when
+    the solve stops before its first step)."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    probs, geoms, bs = small_batch
+    batch = kct.Batch(geoms)
+    outs = [torch.full(g.vol_shape, float("nan"), dtype=torch.float32, device=dev()) for g, _, _ in probs]
+    xs, infos = batch.cgls(bs, 0, outs=outs)
+    for x, inf in zip(xs, infos):
+        assert inf.iterations == 0
+        assert torch.count_nonzero(x).item() == 0
+    batch.close()
+
+
 def test_batch_argument_errors(small_batch):
     import paper_2110_13526_amd as kct
     torch = torch_mod()
