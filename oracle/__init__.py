@@ -69,10 +69,11 @@ def lib():
                                         dp, dp, dp, ip]
         L.oracle_lsqr.restype = ctypes.c_int
         L.oracle_cgls_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, ip]
+                                           ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           dp, dp, dp, ip]
         L.oracle_cgls_ex.restype = ctypes.c_int
         L.oracle_lsqr_ex.argtypes = geo + [dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                                           ctypes.c_double, ctypes.c_int, dp, dp, dp, ip]
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, ip]
         L.oracle_lsqr_ex.restype = ctypes.c_int
         L.oracle_diag_normal.argtypes = geo + [dp]
         L.oracle_diag_normal.restype = None
@@ -89,6 +90,8 @@ def lib():
         L.oracle_tt_diag_normal.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -194,12 +197,16 @@ class SolveResult:
 PROJECTORS = {"siddon": 0, "tt": 1}
 
 
-def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0, projector="siddon"):
+def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0, projector="siddon",
+         store32=False):
     """Algorithm 1 (CGLS with delayed residual) in FP64.
 
     tikhonov = lambda adds lambda^2 |x|^2 to the objective (CGLS on [A; lambda I]);
     recompute_every = k > 0 recomputes e = b - A x after every k-th iteration;
-    projector "siddon" or "tt" selects the operator."""
+    projector "siddon" or "tt" selects the operator;
+    store32 rounds the vectors x, r, d, e, p to single precision after every
+    update (scalars and norms stay double): the single-precision storage form
+    of Section 5, used to measure how far that rounding alone moves the iterates."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
@@ -208,16 +215,17 @@ def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recomput
     it = ctypes.c_int(0)
     stop = lib().oracle_cgls_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
                                 int(bool(literal_update)), float(tikhonov), int(recompute_every),
-                                PROJECTORS[projector], _ptr(hist),
+                                PROJECTORS[projector], int(bool(store32)), _ptr(hist),
                                 ctypes.byref(nb), ctypes.byref(nb0), ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
 
 
-def lsqr(g, b, K, x0=None, err=0.0, damp=0.0, projector="siddon"):
+def lsqr(g, b, K, x0=None, err=0.0, damp=0.0, projector="siddon", store32=False):
     """LSQR (Paige & Saunders) in FP64, iterations aligned with CGLS.
 
-    damp = lambda > 0 solves min |b - A x|^2 + lambda^2 |x - x0|^2."""
+    damp = lambda > 0 solves min |b - A x|^2 + lambda^2 |x - x0|^2;
+    store32 rounds u, v, w and x to single precision after every update."""
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()
@@ -225,7 +233,7 @@ def lsqr(g, b, K, x0=None, err=0.0, damp=0.0, projector="siddon"):
     nb, nb0 = ctypes.c_double(0), ctypes.c_double(0)
     it = ctypes.c_int(0)
     stop = lib().oracle_lsqr_ex(*_gargs(gt), _ptr(b), _ptr(x), int(K), float(err), int(x0 is None),
-                                float(damp), PROJECTORS[projector], _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0),
+                                float(damp), PROJECTORS[projector], int(bool(store32)), _ptr(hist), ctypes.byref(nb), ctypes.byref(nb0),
                                 ctypes.byref(it))
     return SolveResult(x.reshape(g.nz, g.ny, g.nx), it.value, nb.value, nb0.value, stop,
                        hist[: it.value].copy())
@@ -283,3 +291,8 @@ def tt_diag_normal(g):
 
 def num_threads():
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls (results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))

@@ -501,6 +501,17 @@ static double og_dot(const double *a, const double *b, int64_t n)
     return s;
 }
 
+/* Single-precision storage of a solver vector (store32 = 1): every element
+ * rounded to the nearest float.  This is the storage form of the solvers that
+ * Section 5 allows (vectors in float, the scalars kept in double): the oracle
+ * offers it to measure how far that rounding alone moves the iterates of an
+ * otherwise double-precision solve.  store32 = 0 leaves the vector as it is. */
+static void og_store(double *v, int64_t n, int store32)
+{
+    if (!store32) return;
+    for (int64_t i = 0; i < n; ++i) v[i] = (double)(float)v[i];
+}
+
 /* Stop reasons shared by both solvers. */
 enum { OG_STOP_MAXITER = 0, OG_STOP_TOL = 1, OG_STOP_BREAKDOWN = 2, OG_STOP_NUMERIC = 3 };
 
@@ -560,11 +571,13 @@ static void og_cgls_discrepancy(int projector, const int32_t *dims, const double
  * is NB.  recompute_every = k > 0 replaces the update e -= alpha p by
  * e = b - A x after every k-th iteration (the periodic recomputation of the
  * discrepancy that Section 5 discusses).  lambda = 0, k = 0 is Algorithm 1.
+ * store32 = 1 rounds x, r, d, e and p to single precision after every update
+ * (og_store); the norms and scalars stay double.
  */
 int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
                    const double *b, double *x, int K, double err, int x0_is_zero,
-                   int literal_update, double lambda, int recompute_every, int projector, double *history,
-                   double *out_nb, double *out_nb0, int *out_iters)
+                   int literal_update, double lambda, int recompute_every, int projector, int store32,
+                   double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
     const double l2 = lambda * lambda;
     og_t g = og_make(dims, par, angles);
@@ -583,23 +596,29 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
     /* p = A x ; e = b - p */
     if (x0_is_zero) memset(p, 0, sizeof(double) * (size_t)m);
     else og_A(projector, dims, par, angles, x, p);
+    og_store(p, m, store32);
     for (int64_t t = 0; t < m; ++t) e[t] = b[t] - p[t];
+    og_store(e, m, store32);
     NB = sqrt(og_dot(e, e, m));
     /* r = A^T e - lambda^2 x ; d = r ; NR2_old = |r|^2 */
     og_AT(projector, dims, par, angles, e, r);
     if (l2 != 0.0)
         for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
+    og_store(r, n, store32);
     memcpy(d, r, sizeof(double) * (size_t)n);
     double NR2_old = og_dot(r, r, n);
     if (NR2_old == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     /* p = A d ; NP2 = |p|^2 + lambda^2 |d|^2 ; alpha ; x += alpha d ; e -= alpha p ; NB */
     og_A(projector, dims, par, angles, d, p);
+    og_store(p, m, store32);
     double NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
     if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     double alpha = NR2_old / NP2;
     for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
+    og_store(x, n, store32);
     i = 1;
     og_cgls_discrepancy(projector, dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+    og_store(e, m, store32);
     NB = sqrt(og_dot(e, e, m));
     if (history) history[0] = NB0 > 0 ? NB / NB0 : 0.0;
     if (!isfinite(NB)) { stop = OG_STOP_NUMERIC; goto done; }
@@ -607,6 +626,7 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
         og_AT(projector, dims, par, angles, e, r);
         if (l2 != 0.0)
             for (int64_t t = 0; t < n; ++t) r[t] -= l2 * x[t];
+        og_store(r, n, store32);
         double NR2_now = og_dot(r, r, n);
         if (NR2_now == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         double beta = NR2_now / NR2_old;
@@ -614,14 +634,18 @@ int oracle_cgls_ex(const int32_t *dims, const double *par, const double *angles,
             for (int64_t t = 0; t < n; ++t) d[t] = d[t] + beta * r[t];
         else
             for (int64_t t = 0; t < n; ++t) d[t] = r[t] + beta * d[t];
+        og_store(d, n, store32);
         NR2_old = NR2_now;
         og_A(projector, dims, par, angles, d, p);
+        og_store(p, m, store32);
         NP2 = og_dot(p, p, m) + l2 * og_dot(d, d, n);
         if (NP2 == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
         alpha = NR2_old / NP2;
         for (int64_t t = 0; t < n; ++t) x[t] += alpha * d[t];
+        og_store(x, n, store32);
         i = i + 1;
         og_cgls_discrepancy(projector, dims, par, angles, b, x, e, p, alpha, m, recompute_every > 0 && i % recompute_every == 0);
+        og_store(e, m, store32);
         NB = sqrt(og_dot(e, e, m));
         if (og_progress) fprintf(stderr, "oracle cgls: iteration %d of %d\n", i, K);
         if (history) history[i - 1] = NB0 > 0 ? NB / NB0 : 0.0;
@@ -720,7 +744,7 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
                 int literal_update, double *history, double *out_nb, double *out_nb0,
                 int *out_iters)
 {
-    return oracle_cgls_ex(dims, par, angles, b, x, K, err, x0_is_zero, literal_update, 0.0, 0, 0, history, out_nb,
+    return oracle_cgls_ex(dims, par, angles, b, x, K, err, x0_is_zero, literal_update, 0.0, 0, 0, 0, history, out_nb,
                           out_nb0, out_iters);
 }
 
@@ -742,10 +766,12 @@ int oracle_cgls(const int32_t *dims, const double *par, const double *angles,
  * s1 = lambda/rhobar1, psi = s1 phibar, phibar = c1 phibar, and rhobar1 takes
  * rhobar's place; sqrt(phibar^2 + sum psi^2) then estimates the norm of the
  * stacked residual [b - A x; -lambda (x - x0)] (|phibar| when lambda = 0).
+ * store32 = 1 rounds u, v, w and x to single precision after every update
+ * (og_store); the norms and the rotation scalars stay double.
  */
 int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
                    const double *b, double *x, int K, double err, int x0_is_zero, double damp, int projector,
-                   double *history, double *out_nb, double *out_nb0, int *out_iters)
+                   int store32, double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
     og_t g = og_make(dims, par, angles);
     int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -769,28 +795,34 @@ int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
     phibar = beta;
     if (beta == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     for (int64_t t = 0; t < m; ++t) u[t] /= beta;
+    og_store(u, m, store32);
     og_AT(projector, dims, par, angles, u, v);
     double alpha = sqrt(og_dot(v, v, n));
     if (alpha == 0.0) { stop = OG_STOP_BREAKDOWN; goto done; }
     for (int64_t t = 0; t < n; ++t) v[t] /= alpha;
+    og_store(v, n, store32);
     memcpy(w, v, sizeof(double) * (size_t)n);
     double rhobar = alpha;
     while (i < K) {
         /* bidiagonalisation: beta u = A v - alpha u */
         og_A(projector, dims, par, angles, v, tmpm);
         for (int64_t t = 0; t < m; ++t) u[t] = tmpm[t] - alpha * u[t];
+        og_store(u, m, store32);
         beta = sqrt(og_dot(u, u, m));
         int last = (i + 1 == K);
         double alpha_next = 0.0;
         if (beta != 0.0) {
             for (int64_t t = 0; t < m; ++t) u[t] /= beta;
+            og_store(u, m, store32);
             if (!last) {
                 /* alpha v = A^T u - beta v */
                 og_AT(projector, dims, par, angles, u, tmpn);
                 for (int64_t t = 0; t < n; ++t) v[t] = tmpn[t] - beta * v[t];
+                og_store(v, n, store32);
                 alpha_next = sqrt(og_dot(v, v, n));
                 if (alpha_next != 0.0)
                     for (int64_t t = 0; t < n; ++t) v[t] /= alpha_next;
+                og_store(v, n, store32);
             }
         }
         /* damping rotation, then the Givens rotation */
@@ -808,7 +840,9 @@ int oracle_lsqr_ex(const int32_t *dims, const double *par, const double *angles,
         double phi = c * phibar;
         phibar = s * phibar;
         for (int64_t t = 0; t < n; ++t) x[t] += (phi / rho) * w[t];
+        og_store(x, n, store32);
         for (int64_t t = 0; t < n; ++t) w[t] = v[t] - (theta / rho) * w[t];
+        og_store(w, n, store32);
         alpha = alpha_next;
         i = i + 1;
         double nb = sqrt(phibar * phibar + res2);
@@ -830,7 +864,8 @@ int oracle_lsqr(const int32_t *dims, const double *par, const double *angles,
                 const double *b, double *x, int K, double err, int x0_is_zero,
                 double *history, double *out_nb, double *out_nb0, int *out_iters)
 {
-    return oracle_lsqr_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0.0, 0, history, out_nb, out_nb0, out_iters);
+    return oracle_lsqr_ex(dims, par, angles, b, x, K, err, x0_is_zero, 0.0, 0, 0, history, out_nb, out_nb0,
+                          out_iters);
 }
 
 /* ---------------------------------------------------------------- TT footprint projector
@@ -1041,5 +1076,17 @@ int oracle_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the following calls (timing runs on one core); the results do
+ * not depend on it: rays are independent, and each voxel of the slab scatter
+ * sums its rays in ray order whatever the slab partition. */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

@@ -125,6 +125,49 @@ def test_batch_argument_errors(small_batch):
     batch.close()
 
 
+def test_batch_c4_full_size():
+    """The batched workload at its full size: all 48 seeded instances (64^3 to
+    192^3, 60-360 views, 96^2-288^2 detectors, SID 400-700 mm, SDD 800-1400 mm)
+    in one batch, 3 CGLS iterations.  A subset (the smallest and the largest
+    instances, and every eighth) is bitwise equal to its separate
+    kct_cgls_solve; instance 14 is solved from the oracle's data and compared
+    with the stored FP64 oracle result (tests/golden/c4i14_cgls_k3.npz) at the
+    FP32 solver bound."""
+    import paper_2110_13526_amd as kct
+    from tests.golden import make_solver_goldens as mg
+    torch = torch_mod()
+    K = 3
+    gold_i = 14
+    gold = dict(np.load(os.path.join(os.path.dirname(__file__), "golden", "c4i14_cgls_k3.npz"), allow_pickle=False))
+    say("[batch] c4: building 48 full-size instances")
+    probs = []
+    for i in range(48):
+        if i == gold_i:
+            g, x_true, b = mg.problem_data("c4i14")
+            assert mg.b_hash(b) == str(gold["b_sha256"])
+            probs.append((g, x_true, b))
+        else:
+            probs.append(_problem(i, 1.0, torch, oracle_data=False))
+    geoms = [geometry(g) for g, _, _ in probs]
+    bs = [torch.from_numpy(b).to(dev()) for _, _, b in probs]
+    say(f"[batch] c4: {sum(g.n_vox for g, _, _ in probs) / 1e6:.1f} M voxels, "
+        f"{sum(g.n_rays for g, _, _ in probs) / 1e6:.1f} M rays")
+    batch = kct.Batch(geoms)
+    xs, infos = batch.cgls(bs, K, graph=True)
+    assert all(inf.iterations == K for inf in infos)
+    sizes = [g.n_vox * g.n_views for g, _, _ in probs]
+    subset = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), gold_i, *range(0, 48, 8)})
+    for i in subset:
+        x1, info1 = kct.cgls(geoms[i], bs[i], K)
+        assert torch.equal(xs[i], x1), i
+        assert infos[i].nb == info1.nb and infos[i].nb0 == info1.nb0, i
+    idx = np.asarray(gold["idx"], dtype=np.int64)
+    err = rel(to_np(xs[gold_i]).ravel()[idx], gold["x_idx"])
+    say(f"[batch] c4: subset {subset} bitwise equal to separate solves; instance {gold_i} vs oracle rel {err:.3e}")
+    assert err < 1e-4
+    batch.close()
+
+
 @pytest.mark.skipif(not os.environ.get("KCT_BATCH_REPORT"),
                     reason="report run (set KCT_BATCH_REPORT=1): 48 instances of up to 192^3")
 def test_batch_report_c4():

@@ -109,9 +109,13 @@ def test_recompute_every(c1_problem):
 def test_cgls_jacobi(c1_problem, dt):
     """Jacobi scales voxel j by diag(A^T A)_j^(-1/2).  At the cone boundary of this
     truncated geometry the diagonal is tiny (Section 5 names exactly this as the
-    reason the strategy works poorly), so there the single-precision weights'
-    relative rounding is amplified in x.  The discrepancy history and x on the
-    voxels with diag >= 1e-3 max(diag) carry the solver bound."""
+    reason the strategy works poorly): there a voxel is met only by clipped
+    corners of rays, whose short single-precision lengths carry large relative
+    rounding, and x = M z multiplies it by the large M_j.  The solver bound 1e-4
+    applies to the discrepancy history and to the iterate in the variable the
+    preconditioned CGLS works in, z = diag^(1/2) x, over every voxel (relative
+    L2 of diag^(1/2) x with the oracle's diagonal); x itself on the voxels with
+    diag >= 1e-3 max(diag) carries the same bound."""
     import paper_2110_13526_amd as kct
     g, G, x_true, b = c1_problem
     bs, bd = _store(b, dt)
@@ -123,11 +127,14 @@ def test_cgls_jacobi(c1_problem, dt):
     xn = to_np(x)
     err_all = rel(xn, ref.x)
     err = rel(xn[mask], ref.x[mask])
+    sw = np.sqrt(diag)
+    err_z = rel(sw * xn, sw * ref.x)
     herr = float(np.max(np.abs(to_np(info.history) - ref.history) / ref.history))
-    say(f"[variants] cgls jacobi {dt}: x rel {err:.3e} on {mask.mean():.3f} of the voxels ({err_all:.3e} on all), "
-        f"history {herr:.3e}; err vs x_true {rel(xn, x_true):.3f} (plain CGLS {rel(oracle.cgls(g, bs, K).x, x_true):.3f})")
+    say(f"[variants] cgls jacobi {dt}: z = diag^1/2 x rel {err_z:.3e} on all voxels; x rel {err:.3e} on "
+        f"{mask.mean():.3f} of the voxels ({err_all:.3e} on all), history {herr:.3e}; err vs x_true "
+        f"{rel(xn, x_true):.3f} (plain CGLS {rel(oracle.cgls(g, bs, K).x, x_true):.3f})")
     tol = TOL if dt == "f32" else TOL16[dt]
-    assert err < tol and herr < tol
+    assert err_z < tol and err < tol and herr < tol
 
 
 def test_variant_argument_errors(c1_problem):

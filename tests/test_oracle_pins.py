@@ -554,3 +554,58 @@ def test_tt_diag_normal_is_squared_column_norms(variant):
     assert ref.min() >= 0 and ref.max() > 0
     assert np.abs(got - ref).max() <= 1e-12 * ref.max()
     assert rel(got, ref) < 1e-12
+
+
+# ------------------------------------------------------------------ single-precision storage form
+
+@pytest.mark.parametrize("solver", ["cgls", "lsqr"])
+@pytest.mark.parametrize("K", [1, 3, 6])
+def test_store32_iterates_are_floats_near_the_krylov_minimiser(small_problem, solver, K):
+    """The storage form that keeps the solver vectors in single precision
+    (Section 5) rounds every stored element: its iterate is exactly a float
+    array, and it departs from the brute-force Krylov minimiser only by
+    single-precision rounding (a dropped term or a misplaced update would move
+    it by O(1))."""
+    g, A, b = small_problem
+    b32 = b.astype(np.float32).astype(np.float64)
+    ref = krylov_minimiser(A, b32.ravel(), np.zeros(g.n_vox), K)
+    res = getattr(oracle, solver)(g, b32, K, store32=True)
+    x = res.x.ravel()
+    assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+    assert 0.0 < rel(x, ref) < 1e-5
+    full = getattr(oracle, solver)(g, b32, K)
+    assert rel(full.x, ref) < 1e-9
+    np.testing.assert_allclose(res.history, full.history, rtol=1e-5)
+
+
+def test_store32_first_iterate_closed_form(small_problem):
+    """K = 1 with single-precision storage: x_1 = fl(alpha fl(r0)) with
+    r0 = fl(A^T fl(b - fl(A x0))), alpha = |fl(r0)|^2 / |fl(A fl(r0))|^2 in
+    double (the closed form of the first step, rounded where it is stored)."""
+    g, A, b = small_problem
+    b32 = b.astype(np.float32).astype(np.float64).ravel()
+    f = lambda v: v.astype(np.float32).astype(np.float64)  # noqa: E731
+    r0 = f(A.T @ f(b32))
+    p = f(A @ r0)
+    alpha = (r0 @ r0) / (p @ p)
+    res = oracle.cgls(g, b32, 1, store32=True)
+    # the brute-force matrix and the traversal differ by ~1e-13, which can move
+    # an element across a float rounding boundary: allow a few such flips
+    assert rel(res.x, f(alpha * r0)) < 1e-7
+
+
+def test_results_do_not_depend_on_thread_count():
+    """The oracle's projector, scatter backprojector and CGLS give the same bits
+    with one thread as with all (the CPU baseline times both)."""
+    g = ki.t16("offcenter")
+    x = ki.random_volume(g, 5)
+    y = ki.random_projections(g, 6)
+    n = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        a1, r1, c1 = oracle.project(g, x), oracle.backproject(g, y), oracle.cgls(g, y, 3).x
+        oracle.set_num_threads(max(n, 3))
+        a2, r2, c2 = oracle.project(g, x), oracle.backproject(g, y), oracle.cgls(g, y, 3).x
+    finally:
+        oracle.set_num_threads(n)
+    assert np.array_equal(a1, a2) and np.array_equal(r1, r2) and np.array_equal(c1, c2)
