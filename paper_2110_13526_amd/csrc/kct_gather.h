@@ -79,6 +79,16 @@ __host__ __device__ __forceinline__ float med3f(float x, float a, float b)
 #endif
 }
 
+// 1 / x to within a few ulp (bounds only).
+__host__ __device__ __forceinline__ float rcp_approx(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 // Candidate detector columns [ua, ub] of the voxel column whose in-plane centre
 // is (xc, yc): the projective image of its square, bounded around the image of
 // the centre (a bound with margin; the weight function decides).
@@ -110,6 +120,44 @@ __host__ __device__ __forceinline__ void column_interval(const ColStage &cs, flo
     cell_range(ieta, heta, cs.eta_c, cs.inv_a, lo_e, hi_e);
     lo = fmaxf(lo_xi, lo_e);
     hi = fminf(lo_xi + 1.0f, hi_e);
+}
+
+// One staged record, read as a whole (one 128-bit LDS read).
+template <typename A> __host__ __device__ __forceinline__ PixStage<A> load_pix(const PixStage<A> *p) { return *p; }
+template <> __host__ __device__ __forceinline__ PixStage<float> load_pix<float>(const PixStage<float> *p)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    PixStage<float> r;
+    r.zc = v.x;
+    r.czr = v.y;
+    r.le = v.z;
+    r.pad = v.w;
+    return r;
+}
+
+// The candidates of one detector row for one voxel: the rays of the row in the
+// nh (<= NH) staged hit columns starting at prow, whose in-plane xi-intervals
+// are [lo[h], hi[h]], against the voxel's z-planes mb and mb1.  Returns
+// a + sum of w * (L e) (w^2 * le when SQ).
+template <typename A, bool SQ>
+__host__ __device__ __forceinline__ A add_row(const PixStage<A> *prow, int nh, const float (&lo)[NH],
+                                              const float (&hi)[NH], float mb, float mb1, A a)
+{
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        if (h == 0 || h < nh) {
+            const PixStage<A> p = load_pix(prow + h);
+            const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
+            // min(hi, max(b0, b1)) - max(lo, min(b0, b1)) wherever that is positive
+            // (there hi > min(b0, b1) and lo < max(b0, b1), so clamping hi and lo to
+            // [min, max] selects the same operands); elsewhere <= 0 like it.  Clamped
+            // at 0, a candidate that misses adds w * le = 0 and leaves the sum as it
+            // is (le is finite), so no compare and select are needed.
+            const float w = fmaxf(med3f(hi[h], b0, b1) - med3f(lo[h], b0, b1), 0.0f);
+            a = fma_acc(SQ ? w * w : w, p.le, a);
+        }
+    }
+    return a;
 }
 
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
@@ -145,6 +193,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
     }
     const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (index frame)
     const float zz0 = mbz0 + g.zc;         // the same plane as a height above the source plane
+    const float inv_nzb = rcp_approx((float)nzb);
     const float vofs = -g.off_v * g.inv_dv + g.cv;
     const float vofs_lo = vofs - 0.01f, vofs_hi = vofs + 0.01f;
     const int vmax = cv0 + nrow - 1;
@@ -168,46 +217,49 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         if (!(tmax > 0.0f)) continue;  // no column of this group is hit
         // Rows: inside these columns a ray of row height qz meets the z-cell with
         // planes at heights [zz, zz + 1] only if qz lies in [zz, zz + 1] / [Tmin, Tmax].
+        // In row units a plane at height z bounds the rows from below by
+        // f_lo(z) = min(z ra, z rb) and from above by f_hi(z) = max(z ra, z rb).
+        // f_lo is concave and f_hi convex in z, so over the brick's planes the
+        // chords between its lowest and highest plane bound them from the safe
+        // side (exactly equal to them unless the brick straddles the source
+        // plane z = 0): plane p gives lo_p = l0 + p sl and hi_p = h0 + p sh, one
+        // fused multiply-add each.  Their rounding (~1e-5 row) is far inside the
+        // 0.01-row margins.
         const float ra = __builtin_amdgcn_rcpf(tmax) * g.inv_dv, rb = __builtin_amdgcn_rcpf(tmin) * g.inv_dv;
-        // The per-voxel plane heights below do not depend on the column group;
+        const float za = zz0, zb = zz0 + (float)nzb;  // lowest and highest plane of the brick
+        const float a1 = za * ra, a2 = za * rb, b1 = zb * ra, b2 = zb * rb;
+        const float sl = (fminf(b1, b2) - fminf(a1, a2)) * inv_nzb;
+        const float sh = (fmaxf(b1, b2) - fmaxf(a1, a2)) * inv_nzb;
+        const float l0 = fminf(a1, a2) + vofs_lo, h0 = fmaxf(a1, a2) + vofs_hi;
+        // The per-voxel plane values below do not depend on the column group;
         // computed here they stay short-lived (hoisted out of the group loop,
         // all TZ of them would stay live through it).  The empty asm keeps the
         // compiler from hoisting them.
-        float zzb = zz0, mbb = mbz0;
+        float mbb = mbz0;
 #if defined(__HIP_DEVICE_COMPILE__)
-        asm volatile("" : "+v"(zzb), "+v"(mbb));
+        asm volatile("" : "+v"(mbb));
 #endif
-        float pa = zzb * ra, pb = zzb * rb;
         float mb = mbb;  // lower plane of voxel j (exact: an integer or half-integer)
+        const int gofs = (c0 - cu0) + (1 - cv0) * CHC;  // record of row va1 + 1 at va1 * CHC + gofs
 #pragma unroll
         for (int j = 0; j < TZN; ++j) {
-            const float zz1 = zzb + (float)(j + 1);
-            const float na = zz1 * ra, nb = zz1 * rb;
-            // the row offset and the 0.01-row margins in one constant each
-            const float vlo = fminf(pa, pb) + vofs_lo, vhi = fmaxf(na, nb) + vofs_hi;
-            pa = na;
-            pb = nb;
             const float mb1 = mb + 1.0f;
             if (j < nzb) {
-                int va = (int)ceilf(vlo), vb = (int)floorf(vhi);
-                va = va < cv0 ? cv0 : va;
+                // candidate rows va1 + 1 .. vb: floor(lo) + 1 is ceil(lo) except at an
+                // integer lo, whose row lies 0.01 below the true bound and is rightly left out
+                const float vlo = __builtin_fmaf((float)j, sl, l0), vhi = __builtin_fmaf((float)(j + 1), sh, h0);
+                int va1 = (int)floorf(vlo), vb = (int)floorf(vhi);
+                va1 = va1 < cv0 - 1 ? cv0 - 1 : va1;
                 vb = vb > vmax ? vmax : vb;
-                for (int v = va; v <= vb; ++v) {
-                    const PixStage<A> *prow = s_pix + (v - cv0) * CHC + (c0 - cu0);
-#pragma unroll
-                    for (int h = 0; h < NH; ++h) {
-                        if (h < nh) {
-                            const PixStage<A> p = prow[h];
-                            const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
-                            // min(hi, max(b0, b1)) - max(lo, min(b0, b1)) wherever that is positive
-                            // (there hi > min(b0, b1) and lo < max(b0, b1), so clamping hi and lo to
-                            // [min, max] selects the same operands); elsewhere <= 0 like it
-                            const float w = med3f(hi[h], b0, b1) - med3f(lo[h], b0, b1);
-                            // select instead of a branch: one record read, no divergent block
-                            const A t = fma_acc(SQ ? w * w : w, p.le, acc[j]);
-                            acc[j] = w > 0.0f ? t : acc[j];
-                        }
+                if (va1 < vb) {
+                    // the first candidate row outside the loop: most voxels have one
+                    const PixStage<A> *prow = s_pix + (va1 * CHC + gofs);
+                    A a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, acc[j]);
+                    for (int v = va1 + 2; v <= vb; ++v) {
+                        prow += CHC;
+                        a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, a);
                     }
+                    acc[j] = a;
                 }
             }
             mb = mb1;
