@@ -68,6 +68,17 @@ def measured_traffic_bytes(kind, workload, dtype):
     return (ent["fetch_kib"] * cal["fetch_factor"] + ent["write_kib"] * cal["write_factor"]) * 1024.0
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -81,7 +92,8 @@ def main():
     ap.add_argument("--iters", type=int, default=30)
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
-    ap.add_argument("--cpu-views", type=int, default=96, help="views in the CPU-oracle sample")
+    ap.add_argument("--cpu-views", type=int, default=64, help="views in the CPU-oracle sample (all threads)")
+    ap.add_argument("--cpu-views-1t", type=int, default=6, help="views in the one-thread CPU-oracle sample")
     ap.add_argument("--nnz-views", type=int, default=90, help="views sampled to count nonzeros")
     ap.add_argument("--no-precision", action="store_true", help="skip the BF16 / FP16 comparison solves")
     ap.add_argument("--no-tt", action="store_true", help="skip the timing of the TT footprint projector pair")
@@ -138,8 +150,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos = []
+    step_s = []  # each solve returns after its final synchronisation
     for i in range(args.steps):
+        ts = time.perf_counter()
         _, info = kct.cgls(G, b, args.iters, workspace=ws, out=out)
+        step_s.append(time.perf_counter() - ts)
         infos.append(info)
         log(f"[bench] step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
@@ -214,44 +229,88 @@ def main():
 
     cpu = None
     if not args.no_cpu:
+        import oracle
         xs = x_true.astype(np.float64)
-        cstep = max(1, g.n_views // args.cpu_views)
-        idx = np.arange(0, g.n_views, cstep)[: args.cpu_views]
-        subc = g.replace(n_views=len(idx), explicit_angles=g.angles()[idx])
-        t = time.perf_counter()
-        bs = oracle.project(subc, xs)
-        t_a = time.perf_counter() - t
-        t = time.perf_counter()
-        oracle.backproject(subc, bs)
-        t_at = time.perf_counter() - t
-        per_iter = (t_a + t_at) * (g.n_views / subc.n_views)
-        cpu = {"value": round(1.0 / per_iter, 6), "unit": "CGLS iters/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"one A and one A^T over {subc.n_views} of {g.n_views} views (full volume), "
-                         f"{t_a + t_at:.1f} s, scaled by {g.n_views / subc.n_views:g}; vector updates excluded"}
-        log(f"[bench] cpu oracle sample: A {t_a:.2f} s, A^T {t_at:.2f} s on {subc.n_views} views")
 
-    # --- the same solve with 16-bit storage (BF16 / FP16 work vectors and b, FP32 iterate)
+        def oracle_pair(n_views):
+            """One A and one A^T of the oracle over n_views evenly spaced views of
+            the workload (full volume): seconds for each."""
+            cstep = max(1, g.n_views // n_views)
+            idx = np.arange(0, g.n_views, cstep)[:n_views]
+            subc = g.replace(n_views=len(idx), explicit_angles=g.angles()[idx])
+            t = time.perf_counter()
+            bs = oracle.project(subc, xs)
+            t_a = time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.backproject(subc, bs)
+            t_at = time.perf_counter() - t
+            return subc.n_views, t_a, t_at
+
+        threads = oracle.num_threads()
+        nv_all, t_a, t_at = oracle_pair(args.cpu_views)
+        scale = g.n_views / nv_all
+        log(f"[bench] cpu oracle, {threads} threads: A {t_a:.2f} s, A^T {t_at:.2f} s on {nv_all} views")
+        oracle.set_num_threads(1)
+        try:
+            nv_1, t_a1, t_at1 = oracle_pair(args.cpu_views_1t)
+        finally:
+            oracle.set_num_threads(threads)
+        scale1 = g.n_views / nv_1
+        log(f"[bench] cpu oracle, 1 thread: A {t_a1:.2f} s, A^T {t_at1:.2f} s on {nv_1} views")
+        try:
+            affinity = len(os.sched_getaffinity(0))
+        except (AttributeError, OSError):
+            affinity = None
+        cpu = {"value": round(1.0 / ((t_a + t_at) * scale), 6), "unit": "CGLS iters/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"one A and one A^T of the FP64 oracle over {nv_all} of {g.n_views} views (full "
+                         f"volume) with {threads} threads, {t_a + t_at:.1f} s, scaled by {scale:g} to the "
+                         f"workload; vector updates excluded (full solves incl. updates: "
+                         f"profiles/oracle_solver_timings.md)",
+               "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": affinity,
+               "ms_per_A": round(1e3 * t_a * scale, 1), "ms_per_AT": round(1e3 * t_at * scale, 1),
+               "one_thread": {"value": round(1.0 / ((t_a1 + t_at1) * scale1), 7),
+                              "ms_per_A": round(1e3 * t_a1 * scale1, 1),
+                              "ms_per_AT": round(1e3 * t_at1 * scale1, 1),
+                              "sample": f"{nv_1} of {g.n_views} views, {t_a1 + t_at1:.1f} s, scaled by {scale1:g}"}}
+
+    # --- the same solve with the other storage types (BF16 / FP16 work vectors and b, FP32
+    # iterate), with the same warm-up and number of timed steps as the main solve; their steps
+    # are interleaved so that drift of the clock affects both alike
     precision = None
     if not args.no_precision:
-        precision = {args.dtype: {"iters_per_s": round(value, 4), "rel_error_vs_x_true": round(rec_err, 6),
+        def rate_stats(times):
+            r = np.array([args.iters / t for t in times])
+            return {"iters_per_s": round(float(r.mean()), 4), "iters_per_s_std": round(float(r.std()), 4),
+                    "iters_per_s_min": round(float(r.min()), 4), "iters_per_s_max": round(float(r.max()), 4),
+                    "steps": len(times)}
+
+        def rec_error():
+            return (torch.linalg.vector_norm((out - xt).double()) / torch.linalg.vector_norm(xt.double())).item()
+
+        precision = {args.dtype: {**rate_stats(step_s), "rel_error_vs_x_true": round(rec_err, 6),
                                   "relative_discrepancy": round(e_final, 6)}}
-        for name, odt in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16)):
-            if name == args.dtype:
-                continue
-            bo = b.float().to(odt)
-            wso = torch.empty(G.solver_workspace_bytes(odt, "cgls"), dtype=torch.uint8, device=dev)
-            kct.cgls(G, bo, 2, workspace=wso, out=out)  # warm-up of this storage type's kernels
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            _, info = kct.cgls(G, bo, args.iters, workspace=wso, out=out)
-            torch.cuda.synchronize()
-            dto = time.perf_counter() - t
-            err_o = (torch.linalg.vector_norm((out - xt).double()) / torch.linalg.vector_norm(xt.double())).item()
-            precision[name] = {"iters_per_s": round(info.iterations / dto, 4), "rel_error_vs_x_true": round(err_o, 6),
-                               "relative_discrepancy": round(info.nb / info.nb0, 6)}
-            log(f"[bench] {name}: {precision[name]}")
-            del wso, bo
+        others = [(n, d) for n, d in (("f32", torch.float32), ("bf16", torch.bfloat16), ("f16", torch.float16))
+                  if n != args.dtype]
+        inputs = {n: (b.float().to(d), torch.empty(G.solver_workspace_bytes(d, "cgls"), dtype=torch.uint8,
+                                                     device=dev)) for n, d in others}
+        times = {n: [] for n, _ in others}
+        last = {}
+        for i in range(args.warmup + args.steps):
+            for n, _ in others:
+                bo, wso = inputs[n]
+                ts = time.perf_counter()
+                _, info = kct.cgls(G, bo, args.iters, workspace=wso, out=out)
+                if i >= args.warmup:
+                    times[n].append(time.perf_counter() - ts)
+                last[n] = (info, rec_error())
+            log(f"[bench] storage comparison round {i + 1}/{args.warmup + args.steps} done")
+        for n, _ in others:
+            info, err_o = last[n]
+            precision[n] = {**rate_stats(times[n]), "rel_error_vs_x_true": round(err_o, 6),
+                            "relative_discrepancy": round(info.nb / info.nb0, 6)}
+            log(f"[bench] {n}: {precision[n]}")
+        del inputs
         ref = precision["f32"]
         for name, r in precision.items():
             r["speedup_vs_f32"] = round(r["iters_per_s"] / ref["iters_per_s"], 4)
