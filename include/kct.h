@@ -141,6 +141,23 @@ kct_status kct_project_workspace_size(kct_geometry g, kct_dtype dtype, size_t *b
 kct_status kct_project(kct_geometry g, kct_dtype dtype, const void *x, void *b, void *ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* Size of the fixed device array that kct_project_noalloc uses (64 MiB): a
+ * volume of up to 16 Mi FP32 voxels (256^3), 32 Mi 16-bit or 8 Mi FP64 voxels. */
+#define KCT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* kct_project without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Computes exactly what kct_project computes with a
+ * workspace (the same kernels, the same bits), but takes the z-fastest copy of
+ * x in a fixed array of the library (KCT_NOALLOC_SCRATCH_BYTES; each device the
+ * library runs on holds it from the first use until the process ends) instead
+ * of a caller workspace.  It calls no hipMalloc / hipFree and no allocating
+ * library routine.  Every call on one device shares that array and overwrites
+ * what it needs, so calls that overlap in time on one device (different
+ * streams or threads) race; serialise them.  Errors: as kct_project, and
+ * WORKSPACE when n_vox * element size exceeds KCT_NOALLOC_SCRATCH_BYTES. */
+kct_status kct_project_noalloc(kct_geometry g, kct_dtype dtype, const void *x, void *b, hipStream_t stream);
+
 /* Backprojection x := A^T b (Section 2, Eq. 2; standalone backprojection,
  * Section 3), the exact transpose of kct_project.  Voxel-driven gather: no
  * atomics, deterministic.  Errors: INVALID_ARG, UNSUPPORTED, HIP. */
