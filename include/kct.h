@@ -236,12 +236,16 @@ kct_status kct_diag_normal(kct_geometry g, float *out, hipStream_t stream);
 
 /* ---------------------------------------------------------------- batched CGLS
  * Many independent reconstructions, each with its own geometry (volume,
- * detector, views, distances), solved together: every step of Algorithm 1 is
- * one kernel launch that covers all instances, each instance keeps its own
- * double-precision scalars, partial sums and stop flag (so an instance gets
- * exactly the result of its own kct_cgls_solve when both use the same forward
- * variant), and the steps of one iteration are recorded once as a HIP graph and
- * replayed.  FP32 storage. */
+ * detector, views, distances), solved together by CGLS (Section 2,
+ * Algorithm 1).  Every step of an iteration is one launch that covers all
+ * instances; the backprojection, the direction update and the forward
+ * projection are persistent launches (as many workgroups as the device holds
+ * at once) that drain a device work queue of (instance, tiles) items, largest
+ * instance first.  Each instance keeps its own double-precision scalars,
+ * partial sums and stop flag, so it gets exactly the result of its own
+ * kct_cgls_solve when both use the same forward and backprojection variants
+ * (the defaults).  The steps of one iteration are recorded as a HIP graph once
+ * per batch and workspace and replayed.  FP32 storage. */
 typedef struct kct_batch_s *kct_batch;
 
 /* geoms: count geometry handles (host array), all created on the current
@@ -258,12 +262,15 @@ void kct_batch_destroy(kct_batch b);
 kct_status kct_batch_workspace_size(kct_batch b, size_t *bytes);
 
 /* Autotuner: for each instance, time its forward projection with one and with
- * two detector rows per lane (3 launches each after a warm-up, HIP events) and
- * keep the faster for the batch's solves.  cache_path (host, optional): a text
- * file of "<sizes> <rows per lane>" lines; instances whose sizes are listed are
- * not timed, new choices are appended.  ws is scratch (kct_batch_workspace_size
- * bytes, contents overwritten).  Synchronous.  Errors: INVALID_ARG, WORKSPACE,
- * HIP. */
+ * two detector rows per lane, and its backprojection with each brick shape
+ * (16-deep bricks staged in 48-column chunks, 20-deep bricks in 32-column
+ * chunks), 3 launches each after a warm-up (HIP events), and keep the faster of
+ * each for the batch's solves (a tuned instance may then differ from its own
+ * kct_cgls_solve by the rounding of regrouped partial sums).  cache_path
+ * (host, optional): a text file of "<sizes> <rows per lane> <brick shape>"
+ * lines; instances whose sizes are listed are not timed, new choices are
+ * appended.  ws is scratch (kct_batch_workspace_size bytes, contents
+ * overwritten).  Synchronous.  Errors: INVALID_ARG, WORKSPACE, HIP. */
 kct_status kct_batch_tune(kct_batch b, void *ws, size_t ws_bytes, const char *cache_path, hipStream_t stream);
 
 /* For every instance i: x_i := K iterations of CGLS (Algorithm 1) on b_i from
@@ -278,6 +285,13 @@ kct_status kct_batch_tune(kct_batch b, void *ws, size_t ws_bytes, const char *ca
 kct_status kct_batch_cgls_solve(kct_batch b, const float *const *bs, float *const *xs, const kct_solve_opts *opts,
                                 int32_t use_graph, void *ws, size_t ws_bytes, kct_solve_info *infos,
                                 hipStream_t stream);
+
+/* Per-instance latency of the last kct_batch_cgls_solve on this batch:
+ * seconds[i] (host, count values) = time on the device clock from the batch's
+ * set-up (the first step of the solve) to the step at which instance i's solve
+ * stopped (K iterations, tolerance, breakdown).  Errors: INVALID_ARG (no solve
+ * yet), UNSUPPORTED (no device wall clock), HIP. */
+kct_status kct_batch_latencies(kct_batch b, double *seconds);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *kct_last_error(void);

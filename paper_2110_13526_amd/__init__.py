@@ -150,6 +150,14 @@ class Geometry:
         _lib.check(_lib.load().kct_solver_workspace_size(self.handle, _dtype_code(dtype), code, ctypes.byref(n)))
         return n.value
 
+    def latencies(self):
+        """Seconds from the set-up of the last batched solve to each instance's
+        completion, on the device clock (see kct_batch_latencies)."""
+        n = len(self.geometries)
+        out = (ctypes.c_double * n)()
+        _lib.check(_lib.load().kct_batch_latencies(self.handle, out))
+        return list(out)
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             _lib.load().kct_geometry_destroy(self._h)
@@ -301,11 +309,13 @@ def lsqr(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = Fals
 class Batch:
     """Batched CGLS over independent reconstructions with their own geometries
     (kct_batch_* in include/kct.h): every step of Algorithm 1 is one launch for
-    all instances, one iteration is replayed as a HIP graph.  FP32 storage.
+    all instances (persistent work-queue launches for the projector steps), one
+    iteration is replayed as a HIP graph.  FP32 storage.
 
         batch = Batch([g1, g2, ...])
-        batch.tune(cache="tune.txt")            # optional: forward variant per instance
+        batch.tune(cache="tune.txt")            # optional: forward and backprojection variants
         xs, infos = batch.cgls([b1, b2, ...], K)
+        seconds = batch.latencies()             # per-instance completion times of that solve
     """
 
     def __init__(self, geometries: Sequence[Geometry]):
@@ -343,7 +353,7 @@ class Batch:
         return self._ws
 
     def tune(self, cache: Optional[str] = None, workspace=None):
-        """Choose each instance's forward variant by timing (see kct_batch_tune)."""
+        """Choose each instance's forward and backprojection variants by timing (see kct_batch_tune)."""
         torch = _torch()
         ws = self._workspace(workspace)
         with torch.cuda.device(self.device):
@@ -377,6 +387,14 @@ class Batch:
             _lib.check(st)
         res = [SolveInfo(i.iterations, i.nb0, i.nb, i.nr2, i.stop_reason) for i in infos]
         return outs, res
+
+    def latencies(self):
+        """Seconds from the set-up of the last batched solve to each instance's
+        completion, on the device clock (see kct_batch_latencies)."""
+        n = len(self.geometries)
+        out = (ctypes.c_double * n)()
+        _lib.check(_lib.load().kct_batch_latencies(self.handle, out))
+        return list(out)
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -23,6 +23,7 @@ EXPORTS = (
     "kct_project", "kct_backproject", "kct_solver_workspace_size", "kct_cgls_solve", "kct_lsqr_solve",
     "kct_diag_normal", "kct_batch_create", "kct_batch_destroy", "kct_batch_workspace_size", "kct_batch_tune",
     "kct_batch_cgls_solve", "kct_geometry_set_projector", "kct_last_error", "kct_project_noalloc",
+    "kct_batch_latencies",
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -86,6 +87,8 @@ def load():
     L.kct_project.restype = st
     L.kct_project_noalloc.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.kct_project_noalloc.restype = st
+    L.kct_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.kct_batch_latencies.restype = st
     L.kct_backproject.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.kct_backproject.restype = st
     L.kct_solver_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]

@@ -19,6 +19,7 @@
 namespace kct {
 
 constexpr int NXCD = 8;
+static_assert(BX == 16 && BY == 16, "the shadow table (ShadowParam) is built for columns of 16 x 16 voxels");
 
 __device__ __forceinline__ double bwd_block_sum(double v)
 {
@@ -33,17 +34,16 @@ __device__ __forceinline__ double bwd_block_sum(double v)
 
 // backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
 // backprojection into one volume; its partial sum goes to partials[w].
-template <typename T, int EPI, int TZB>
+// s_pix / s_col: LDS for CH_ROWS x CHC staged pixels and CHC columns.
+template <typename T, int EPI, int TZB, int CHC>
 __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *__restrict__ proj,
                                                T *__restrict__ out, T *__restrict__ out_z,
                                                const Scalars *__restrict__ sc, double *__restrict__ partials,
-                                               int nbx, int nby, int nbz, const float *__restrict__ aux)
+                                               int nbx, int nby, int nbz, const float *__restrict__ aux,
+                                               PixStage<acc_t<T>> *s_pix, ColStage *s_col)
 {
     using A = acc_t<T>;
     constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
-    constexpr int CHC = ch_cols(TZB);
-    __shared__ PixStage<A> s_pix[CH_ROWS * CHC];
-    __shared__ ColStage s_col[CHC];
 
     // XCD-aware brick assignment
     const int nb = nbx * nby * nbz;
@@ -55,11 +55,10 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     const int nzb = g.nz - iz0 < TZB ? g.nz - iz0 : TZB;
     const bool valid = ix < g.nx && iy < g.ny;
 
-    // brick corners in world coordinates (clamped to the volume)
-    const int ex = (bx + 1) * BX < g.nx ? (bx + 1) * BX : g.nx;
-    const int ey = (by + 1) * BY < g.ny ? (by + 1) * BY : g.ny;
-    const float wx0 = g.x0 + (float)(bx * BX) * g.vx, wx1 = g.x0 + (float)ex * g.vx;
-    const float wy0 = g.y0 + (float)(by * BY) * g.vy, wy1 = g.y0 + (float)ey * g.vy;
+    // the brick's column in the shadow table, and its lowest and highest plane
+    // (heights above the source plane, mm)
+    const int sbi = by * g.sbx + bx;
+    const size_t sbxy = (size_t)g.sbx * g.sby;
     const float wz0 = g.z0 + (float)iz0 * g.vz, wz1 = g.z0 + (float)(iz0 + nzb) * g.vz;
 
     // rays parallel to the z-planes lie in z-cell pcell; their staged zc is
@@ -73,28 +72,19 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 
     for (int k = 0; k < g.nviews; ++k) {
         const ViewParam vp = g.views[k];
-        // 1. shadow of the brick: in every wavefront lanes 0..7 project one
-        //    corner each and the bounds are combined across those lanes, so
-        //    each wavefront holds them without a barrier (the same numbers in all)
+        // 1. shadow of the brick: its column's detector columns from the table
+        //    (uniform: scalar loads), its rows from the heights of its lowest and
+        //    highest plane seen at the column's extreme inverse depths, widened
+        //    by 0.01 row against rounding
         int u0, u1, v0, v1;
         {
-            const int c = threadIdx.x & 7;
-            float fu, fv;
-            project_point(g, vp, (c & 1) ? wx1 : wx0, (c & 2) ? wy1 : wy0, (c & 4) ? wz1 : wz0, fu, fv);
-            float umin = fu, umax = fu, vmin = fv, vmax = fv;
-            for (int off = 1; off < 8; off <<= 1) {
-                umin = fminf(umin, __shfl_xor(umin, off, 8));
-                umax = fmaxf(umax, __shfl_xor(umax, off, 8));
-                vmin = fminf(vmin, __shfl_xor(vmin, off, 8));
-                vmax = fmaxf(vmax, __shfl_xor(vmax, off, 8));
-            }
-            // a ray through the brick meets the detector inside the convex hull of the
-            // projected corners: the pixel centres in [min, max], widened by 0.01 pixel
-            // against rounding (relative ~1e-7 of the coordinates)
-            const int a0 = (int)ceilf(umin - 0.01f), a1 = (int)floorf(umax + 0.01f);
-            const int b0 = (int)ceilf(vmin - 0.01f), b1 = (int)floorf(vmax + 0.01f);
-            u0 = __builtin_amdgcn_readfirstlane(a0 < 0 ? 0 : a0);
-            u1 = __builtin_amdgcn_readfirstlane(a1 > g.nu - 1 ? g.nu - 1 : a1);
+            const ShadowParam sh = g.shadows[(size_t)k * sbxy + sbi];
+            u0 = sh.u0;
+            u1 = sh.u1;
+            const float p0 = wz0 * sh.rmin, p1 = wz0 * sh.rmax, p2 = wz1 * sh.rmin, p3 = wz1 * sh.rmax;
+            const float zlo = fminf(fminf(p0, p1), fminf(p2, p3)), zhi = fmaxf(fmaxf(p0, p1), fmaxf(p2, p3));
+            const int b0 = (int)ceilf(__builtin_fmaf(zlo, g.kv, g.fv0) - 0.01f);
+            const int b1 = (int)floorf(__builtin_fmaf(zhi, g.kv, g.fv0) + 0.01f);
             v0 = __builtin_amdgcn_readfirstlane(b0 < 0 ? 0 : b0);
             v1 = __builtin_amdgcn_readfirstlane(b1 > g.nv - 1 ? g.nv - 1 : b1);
         }
@@ -108,7 +98,10 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 //    per column the in-plane parameters
                 //    (pixel t = r * ncol + c; t steps by 256: r by dr, c by dc, with carry)
                 {
-                    int r = (int)threadIdx.x / ncol, c = (int)threadIdx.x - r * ncol;
+                    // threadIdx.x / ncol through a reciprocal: (t + 0.5) / ncol lies at least
+                    // 0.5 / ncol >= 0.01 from an integer, the product's rounding below 1e-4
+                    const float rn = __builtin_amdgcn_rcpf((float)ncol);
+                    int r = (int)(((float)threadIdx.x + 0.5f) * rn), c = (int)threadIdx.x - r * ncol;
                     const int dr = 256 / ncol, dc = 256 - dr * ncol;
                     for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
                         // the projection value first: its load overlaps the parameter loads
@@ -175,7 +168,11 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward
                                                                                 const float *__restrict__ aux)
 {
     if (skip && *skip) return;
-    backward_block<T, EPI, TZB>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux);
+    constexpr int CHC = ch_cols(TZB);
+    __shared__ PixStage<acc_t<T>> s_pix[CH_ROWS * CHC];
+    __shared__ ColStage s_col[CHC];
+    backward_block<T, EPI, TZB, CHC>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
+                                     s_col);
 }
 
 // Brick depth of a single backprojection: TZ_DEEP voxels per lane when the
@@ -195,30 +192,91 @@ static void bwd_grid(const GeoDev &g, int tz, int &nbx, int &nby, int &nbz)
     nbz = (g.nz + tz - 1) / tz;
 }
 
-// Grid of the batched backprojection (bricks of depth TZ for every instance).
-int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz)
+// Backprojection variants of the batched form (BwdVariant): brick depth and
+// staged chunk width.
+__host__ __device__ constexpr int variant_depth(int v) { return v == BWD_V20 ? TZ_DEEP : TZ; }
+constexpr int VARIANT_LDS_COLS = 48;  // the widest chunk of the variants
+
+int64_t backward_variant_grid(const GeoDev &g, int variant, int &nbx, int &nby, int &nbz)
 {
-    bwd_grid(g, TZ, nbx, nby, nbz);
+    bwd_grid(g, variant_depth(variant), nbx, nby, nbz);
     return (int64_t)nbx * nby * nbz;
 }
 
-// Batched r = A^T e with |r|^2 partials for every instance.
-__global__ __launch_bounds__(256, 6) void kb_backward(const BatchInst *__restrict__ B,
-                                                      const int64_t *__restrict__ off, int count)
+// The variant a single solve would use: its block decomposition (and so its
+// partial sums) is that of kct_cgls_solve.
+int backward_default_variant(const GeoDev &g) { return bwd_depth(g) == TZ_DEEP ? BWD_V20 : BWD_V16; }
+
+// One tile (brick) of variant v of instance bi's r = A^T e with |r|^2 partials.
+__device__ __forceinline__ void batch_backward_tile(const BatchInst *bi, int lw, PixStage<float> *s_pix,
+                                                    ColStage *s_col)
 {
-    const int64_t w = blockIdx.x;
-    const int i = batch_find(off, count, w);
-    const BatchInst *bi = B + i;
-    if (bi->sc->done) return;
-    const int64_t lw = w - off[i];
-    if (lw >= (int64_t)bi->nbx * bi->nby * bi->nbz) return;  // padding of the instance's grid
-    backward_block<float, BWD_NORM, TZ>(bi->g, (int)lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx, bi->nby,
-                                        bi->nbz, nullptr);
+    if (bi->bwd_v == BWD_V20)
+        backward_block<float, BWD_NORM, TZ_DEEP, 32>(bi->g, lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx,
+                                                    bi->nby, bi->nbz, nullptr, s_pix, s_col);
+    else
+        backward_block<float, BWD_NORM, TZ, 48>(bi->g, lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx, bi->nby,
+                                               bi->nbz, nullptr, s_pix, s_col);
 }
 
-hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st)
+// Persistent batched r = A^T e: every workgroup takes items from the queue
+// until it is empty (see BatchInst); each item is up to BATCH_ITEM_BWD bricks
+// of one instance.
+__global__ __launch_bounds__(256, 6) void kp_backward(const BatchInst *__restrict__ B,
+                                                      const int64_t *__restrict__ off, int count,
+                                                      BatchQueue *__restrict__ q)
 {
-    hipLaunchKernelGGL(kb_backward, dim3((unsigned)blocks), dim3(256), 0, st, B, off, count);
+    __shared__ PixStage<float> s_pix[CH_ROWS * VARIANT_LDS_COLS];
+    __shared__ ColStage s_col[VARIANT_LDS_COLS];
+    const int64_t total = off[count];
+    for (;;) {
+        const int64_t item = batch_pop(q);
+        if (item >= total) break;
+        const int i = batch_find(off, count, item);
+        const BatchInst *bi = B + i;
+        if (bi->sc->done) continue;
+        const int64_t t0 = (item - off[i]) * BATCH_ITEM_BWD;
+        const int64_t t1 = t0 + BATCH_ITEM_BWD < bi->nbk ? t0 + BATCH_ITEM_BWD : bi->nbk;
+        for (int64_t t = t0; t < t1; ++t) {
+            batch_backward_tile(bi, (int)t, s_pix, s_col);
+            __syncthreads();  // the tile's block sum is read before the next tile writes it
+        }
+    }
+    batch_exit(q);
+}
+
+hipError_t batch_backward_occupancy(int &per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp_backward, 256, 0);
+}
+
+hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid,
+                                 hipStream_t st)
+{
+    hipLaunchKernelGGL(kp_backward, dim3((unsigned)grid), dim3(256), 0, st, B, off, count, q);
+    return hipGetLastError();
+}
+
+// A single plain backprojection with batched-form variant v (the tuner times these).
+template <int TZB, int CHC>
+__global__ __launch_bounds__(256, 6) void k_backward_v(GeoDev g, const float *__restrict__ proj,
+                                                       float *__restrict__ out, int nbx, int nby, int nbz)
+{
+    __shared__ PixStage<float> s_pix[CH_ROWS * CHC];
+    __shared__ ColStage s_col[CHC];
+    backward_block<float, BWD_PLAIN, TZB, CHC>(g, blockIdx.x, proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
+                                               nullptr, s_pix, s_col);
+}
+
+hipError_t launch_backward_variant(const GeoDev &g, int variant, const float *proj, float *out, hipStream_t st)
+{
+    int nbx, nby, nbz;
+    const int64_t nb = backward_variant_grid(g, variant, nbx, nby, nbz);
+    if (variant == BWD_V20)
+        hipLaunchKernelGGL((k_backward_v<TZ_DEEP, 32>), dim3((unsigned)nb), dim3(256), 0, st, g, proj, out, nbx, nby,
+                           nbz);
+    else
+        hipLaunchKernelGGL((k_backward_v<TZ, 48>), dim3((unsigned)nb), dim3(256), 0, st, g, proj, out, nbx, nby, nbz);
     return hipGetLastError();
 }
 

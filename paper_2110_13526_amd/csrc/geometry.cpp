@@ -112,7 +112,9 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
         vp.c = (float)c;
         vp.s = (float)s;
         vp.dom = dom;
-        vp.pad[0] = vp.pad[1] = vp.pad[2] = 0;
+        vp.dn = (float)(0.5 * (vol.vx * std::fabs(s) + vol.vy * std::fabs(c)));
+        vp.dd = (float)(0.5 * (vol.vx * std::fabs(c) + vol.vy * std::fabs(s)));
+        vp.pad = 0;
         const double vxi = dom == 0 ? vol.vx : vol.vy, veta = dom == 0 ? vol.vy : vol.vx;
         const double cxi = dom == 0 ? ox : oy, ceta = dom == 0 ? oy : ox;
         const double Sxi = dom == 0 ? Sx : Sy, Seta = dom == 0 ? Sy : Sx;
@@ -171,10 +173,55 @@ kct_status geometry_tables(const kct_volume_desc &vol, const kct_cone_desc &cone
     d.projector = KCT_PROJECTOR_SIDDON;
     d.sid = (float)cone.sid;
     d.cv = 0.5f * (float)(nv - 1);
+    d.ku = (float)(cone.sdd / cone.du);
+    d.kv = (float)(cone.sdd / cone.dv);
+    d.fu0 = (float)(0.5 * (nu - 1) - cone.off_u / cone.du);
+    d.fv0 = (float)(0.5 * (nv - 1) - cone.off_v / cone.dv);
     d.cols = nullptr;
     d.rows = nullptr;
     d.views = nullptr;
+    d.shadows = nullptr;
+    d.sbx = d.sby = 0;
     return KCT_OK;
+}
+
+// The shadow table of the brick gather (ShadowParam), in double precision: for
+// every view and every column of 16 x 16 voxel bricks, the detector columns
+// whose pixel centres lie in the hull of its four in-plane corners' images
+// widened by 0.01 column, and the extreme inverse depths of those corners.
+static void shadow_table(const kct_volume_desc &vol, const kct_cone_desc &cone, std::vector<ShadowParam> &sh,
+                         int &sbx, int &sby)
+{
+    sbx = (vol.nx + 15) / 16;
+    sby = (vol.ny + 15) / 16;
+    sh.assign((size_t)cone.n_views * sbx * sby, ShadowParam{});
+    const double X0 = vol.cx - 0.5 * vol.nx * vol.vx, Y0 = vol.cy - 0.5 * vol.ny * vol.vy;
+    const double cu = 0.5 * (cone.nu - 1);
+    for (int k = 0; k < cone.n_views; ++k) {
+        const double t = view_angle(cone, k);
+        const double c = std::cos(t), s = std::sin(t);
+        const double Sx = cone.sid * c, Sy = cone.sid * s;
+        for (int by = 0; by < sby; ++by)
+            for (int bx = 0; bx < sbx; ++bx) {
+                const double xs[2] = {X0 + 16.0 * bx * vol.vx, X0 + std::min(16 * (bx + 1), vol.nx) * vol.vx};
+                const double ys[2] = {Y0 + 16.0 * by * vol.vy, Y0 + std::min(16 * (by + 1), vol.ny) * vol.vy};
+                double umin = INFINITY, umax = -INFINITY, rmin = INFINITY, rmax = -INFINITY;
+                for (int cc = 0; cc < 4; ++cc) {
+                    const double dx = xs[cc & 1] - Sx, dy = ys[cc >> 1] - Sy;
+                    const double num = -s * dx + c * dy, den = -c * dx - s * dy;  // den > 0 (checked above)
+                    const double u = (cone.sdd * num / den - cone.off_u) / cone.du + cu;
+                    umin = std::min(umin, u);
+                    umax = std::max(umax, u);
+                    rmin = std::min(rmin, 1.0 / den);
+                    rmax = std::max(rmax, 1.0 / den);
+                }
+                ShadowParam &p = sh[((size_t)k * sby + by) * sbx + bx];
+                p.u0 = std::max(0, (int)std::ceil(umin - 0.01));
+                p.u1 = std::min(cone.nu - 1, (int)std::floor(umax + 0.01));
+                p.rmin = (float)rmin;
+                p.rmax = (float)rmax;
+            }
+    }
 }
 
 kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone, Geometry *g)
@@ -189,10 +236,12 @@ kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone,
     g->cone.angles = nullptr;  // the handle does not keep the caller's pointer
     GeoDev &d = g->dev;
 
+    std::vector<ShadowParam> shadows;
+    shadow_table(vol, cone, shadows, d.sbx, d.sby);
     size_t cb = cols.size() * sizeof(ColParam), rb = rows.size() * sizeof(RowParam);
-    size_t vb = views.size() * sizeof(ViewParam);
+    size_t vb = views.size() * sizeof(ViewParam), sb = shadows.size() * sizeof(ShadowParam);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    size_t total = al(cb) + al(rb) + al(vb);
+    size_t total = al(cb) + al(rb) + al(vb) + al(sb);
     if (hipGetDevice(&g->device) != hipSuccess) {
         set_error("kct_geometry_create: hipGetDevice failed");
         return KCT_ERR_HIP;
@@ -207,6 +256,7 @@ kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone,
     e = hipMemcpy(base, cols.data(), cb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + al(cb), rows.data(), rb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(base + al(cb) + al(rb), views.data(), vb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(base + al(cb) + al(rb) + al(vb), shadows.data(), sb, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(p);
         set_error(std::string("kct_geometry_create: table upload failed: ") + hipGetErrorString(e));
@@ -217,6 +267,7 @@ kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone,
     d.cols = (const ColParam *)base;
     d.rows = (const RowParam *)(base + al(cb));
     d.views = (const ViewParam *)(base + al(cb) + al(rb));
+    d.shadows = (const ShadowParam *)(base + al(cb) + al(rb) + al(vb));
     return KCT_OK;
 }
 

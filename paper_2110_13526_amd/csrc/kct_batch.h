@@ -20,4 +20,30 @@ __device__ __forceinline__ int batch_find(const int64_t *__restrict__ off, int c
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
+// The next item of a persistent step's queue, the same in every thread of the
+// workgroup.  Items are handed out in increasing order; every workgroup keeps
+// taking items until it draws one beyond the last, so the queue always drains.
+__device__ __forceinline__ int64_t batch_pop(BatchQueue *q)
+{
+    __shared__ unsigned s_item;
+    __syncthreads();  // the previous item's readers are done with s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(&q->next, 1u);
+    __syncthreads();
+    return (int64_t)s_item;
+}
+
+// Leave a persistent step: the last workgroup to leave (every other one has
+// drawn its final item) resets the queue for the next launch of the step.
+__device__ __forceinline__ void batch_exit(BatchQueue *q)
+{
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned n = atomicAdd(&q->exited, 1u);
+        if (n == gridDim.x - 1) {
+            atomicExch(&q->next, 0u);
+            atomicExch(&q->exited, 0u);
+        }
+    }
+}
+
 }  // namespace kct

@@ -56,6 +56,16 @@ template <> struct PixStage<double> {  // the same 16 bytes with a double L * e
     double le;
 };
 
+// 1 / x to within a few ulp (bounds only).
+__host__ __device__ __forceinline__ float rcp_approx(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+
 // Detector coordinates (column, row; fractional pixel indices) of the ray
 // through world point (px, py, pz) in view vp.  Used for bounds only.
 __host__ __device__ __forceinline__ void project_point(const GeoDev &g, const ViewParam &vp, float px, float py,
@@ -64,9 +74,9 @@ __host__ __device__ __forceinline__ void project_point(const GeoDev &g, const Vi
     const float dx = px - vp.sx, dy = py - vp.sy;
     const float num = -vp.s * dx + vp.c * dy;
     const float den = -vp.c * dx - vp.s * dy;  // depth along the central ray (> 0)
-    const float sc = g.sdd * __builtin_amdgcn_rcpf(den);
-    fu = (num * sc - g.off_u) * g.inv_du + g.cu;
-    fv = (pz * sc - g.off_v) * g.inv_dv + g.cv;
+    const float inv = rcp_approx(den);
+    fu = __builtin_fmaf(num * inv, g.ku, g.fu0);
+    fv = __builtin_fmaf(pz * inv, g.kv, g.fv0);
 }
 
 // Median of x, a and b: x clamped to the interval between a and b.
@@ -79,33 +89,21 @@ __host__ __device__ __forceinline__ float med3f(float x, float a, float b)
 #endif
 }
 
-// 1 / x to within a few ulp (bounds only).
-__host__ __device__ __forceinline__ float rcp_approx(float x)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_rcpf(x);
-#else
-    return 1.0f / x;
-#endif
-}
-
 // Candidate detector columns [ua, ub] of the voxel column whose in-plane centre
 // is (xc, yc): the projective image of its square, bounded around the image of
 // the centre (a bound with margin; the weight function decides).
 __host__ __device__ __forceinline__ void voxel_columns(const GeoDev &g, const ViewParam &vp, float xc, float yc,
                                                        int &ua, int &ub)
 {
+    // bounds only: fused multiply-adds round differently from the separate
+    // operations by ~1e-7 relative, far inside the 0.01-column margin
     const float dx = xc - vp.sx, dy = yc - vp.sy;
-    const float num = -vp.s * dx + vp.c * dy;
-    const float den = -vp.c * dx - vp.s * dy;
-    const float dn = 0.5f * (g.vx * fabsf(vp.s) + g.vy * fabsf(vp.c));  // half extent along e_u
-    const float dd = 0.5f * (g.vx * fabsf(vp.c) + g.vy * fabsf(vp.s));  // half extent along depth
-    const float inv = __builtin_amdgcn_rcpf(den);
-    const float inv2 = __builtin_amdgcn_rcpf(den - dd);
-    const float uc = g.sdd * num * inv;
-    const float hw = g.sdd * (dn + dd * fabsf(num) * inv) * inv2;
-    const float fc = (uc - g.off_u) * g.inv_du + g.cu;
-    const float hc = hw * g.inv_du + 0.01f;
+    const float num = __builtin_fmaf(vp.c, dy, -vp.s * dx);
+    const float den = __builtin_fmaf(-vp.c, dx, -vp.s * dy);
+    const float inv = rcp_approx(den);
+    const float inv2 = rcp_approx(den - vp.dd);  // dd: half extent along depth, dn: along e_u
+    const float fc = __builtin_fmaf(num * inv, g.ku, g.fu0);
+    const float hc = __builtin_fmaf(__builtin_fmaf(vp.dd * fabsf(num), inv, vp.dn) * inv2, g.ku, 0.01f);
     ua = (int)ceilf(fc - hc);
     ub = (int)floorf(fc + hc);
 }
@@ -194,8 +192,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
     const float mbz0 = (float)iz0 - g.hz;  // lower plane of the first voxel (index frame)
     const float zz0 = mbz0 + g.zc;         // the same plane as a height above the source plane
     const float inv_nzb = rcp_approx((float)nzb);
-    const float vofs = -g.off_v * g.inv_dv + g.cv;
-    const float vofs_lo = vofs - 0.01f, vofs_hi = vofs + 0.01f;
+    const float vofs_lo = g.fv0 - 0.01f, vofs_hi = g.fv0 + 0.01f;
     const int vmax = cv0 + nrow - 1;
     for (int c0 = ha; c0 <= hb; c0 += NH) {
         // xi-intervals of up to NH hit columns, and the range of T = tcv + xi gz

@@ -55,7 +55,17 @@ struct ViewParam {   // per view
     float sx, sy;    // source position [mm]
     float c, s;      // cos and sin of the view angle
     int dom;         // 0: xi = x, eta = y;  1: xi = y, eta = x
-    int pad[3];
+    float dn, dd;    // half extent of a voxel's square across (e_u) and along the central ray [mm]
+    int pad;
+};
+
+// Per (view, column of 16 x 16 voxel bricks): the detector columns that the
+// brick column's rays can meet (its shadow, clamped to the detector; u0 > u1
+// when none), and the extreme inverse depths of its four in-plane corners, from
+// which a brick of any z-extent bounds its detector rows.
+struct ShadowParam {
+    int u0, u1;
+    float rmin, rmax;  // 1 / depth along the central ray [1/mm]
 };
 
 // Everything the kernels need, passed by value.
@@ -69,11 +79,17 @@ struct GeoDev {
     float sdd, du, dv, off_u, off_v;
     float inv_du, inv_dv;
     float cu, cv;            // (nu - 1)/2, (nv - 1)/2
+    // Detector coordinates as fractional pixel indices, for bounds:
+    // column = ku * (lateral / depth) + fu0, row = kv * (height / depth) + fv0
+    float ku, kv;            // sdd / du, sdd / dv
+    float fu0, fv0;          // cu - off_u / du, cv - off_v / dv
     int projector;           // KCT_PROJECTOR_SIDDON or KCT_PROJECTOR_TT (host-side dispatch)
     float sid;               // source to rotation axis [mm]
     const ColParam *cols;    // [nviews][nu]
     const RowParam *rows;    // [nv]
     const ViewParam *views;  // [nviews]
+    const ShadowParam *shadows;  // [nviews][sby][sbx] (16 x 16 brick columns)
+    int sbx, sby;
 };
 
 // Double-precision solver state kept on the device (one per solve).
@@ -98,6 +114,8 @@ struct Scalars {
     double *history;
     int iters, done, stop, maxiter;
     int skip_bwd, pad0, pad1, pad2;
+    // device wall-clock stamps (batched solves): set up, and stopped
+    unsigned long long t_start, t_done;
 };
 
 enum FinalizeOp {
@@ -206,18 +224,24 @@ hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_
 
 // ---------------------------------------------------------------- batched CGLS
 // One instance of a batched solve as the batched kernels see it (single
-// precision storage).  Each batched launch covers every instance: workgroup w
-// of a batched grid belongs to the instance i with off[i] <= w < off[i + 1]
-// (the per-instance grids are padded to multiples of 64 so the XCD-aware
-// workgroup orders of the single-instance kernels carry over), and runs
-// workgroup w - off[i] of that instance's own grid, with that instance's
-// partial sums and scalars; an instance whose solve has stopped skips its work.
+// precision storage).  The heavy steps of an iteration (backprojection,
+// direction update, forward projection) run as persistent launches: a grid
+// sized to the resident capacity of the device drains a queue of items, an
+// item being up to a fixed number of consecutive tiles (workgroups of the
+// instance's own single-solve grid) of one instance; items are numbered
+// instance by instance in the batch's order (largest work first), so
+// item q belongs to the instance i with off[i] <= q < off[i + 1].  Each tile
+// is processed exactly as the instance's own solve would process it, with
+// that instance's partial sums and scalars, so a batched solve returns the
+// bits of the separate solves; an instance whose solve has stopped skips its
+// items.
 struct BatchInst {
     GeoDev g;
     int64_t n, m;               // voxels, rays
-    int fwd_r;                  // rows per lane of its forward variant
-    int nbx, nby, nbz;          // backward brick grid
-    int64_t nf, nbk;            // workgroups of its forward and backward grids (partials per launch)
+    int fwd_r;                  // rows per lane of its forward variant (1 or 2)
+    int bwd_v;                  // its backprojection variant (BWD_VARIANTS)
+    int nbx, nby, nbz;          // backward brick grid of that variant
+    int64_t nf, nbk, ndir;      // tiles of its forward, backward and direction grids (partials per launch)
     const float *b;
     float *x;
     Scalars *sc;
@@ -225,18 +249,41 @@ struct BatchInst {
     float *d, *dz, *r, *e, *p;
 };
 
-enum BatchGrid { BG_FWD = 0, BG_BWD, BG_DIR, BG_STREAM, BG_COUNT };  // offset tables, each count + 1 long
+// Backprojection variants of the batched form: brick depth and staged chunk
+// width (columns).  0: 16-deep bricks, 48-column chunks; 1: 20-deep bricks,
+// 32-column chunks (the single solve's choice for large volumes).
+enum BwdVariant { BWD_V16 = 0, BWD_V20 = 1, BWD_VARIANTS = 2 };
 
-hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st);
-hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st);
+enum BatchGrid { BG_FWD = 0, BG_BWD, BG_DIR, BG_STREAM, BG_COUNT };  // item tables, each count + 1 long
+// Tiles per queue item of each persistent step: items must far outnumber the
+// resident workgroups for the queue to balance the load (a brick of the
+// backprojection is a long task, a forward or direction tile a short one).
+constexpr int BATCH_ITEM_FWD = 16, BATCH_ITEM_BWD = 1, BATCH_ITEM_DIR = 8;
+// Queue state of one persistent step: the next item, and the workgroups that
+// have left (the last one resets both for the next launch).
+struct BatchQueue {
+    unsigned next, exited, pad0, pad1;
+};
+
+hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid,
+                                hipStream_t st);
+hipError_t launch_batch_backward(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid,
+                                 hipStream_t st);
 // op: one of the batched vector steps below
 enum BatchVecOp { BV_INIT = 0, BV_NORM_B, BV_X0_E, BV_CGLS_X, BV_CGLS_E };
 hipError_t launch_batch_vec(const BatchInst *B, int count, int op, int maxiter, double err, hipStream_t st);
-hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, int64_t blocks, int first,
+hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid, int first,
                             hipStream_t st);
 // finalize of every instance; kind: which grid produced the partials (BatchGrid)
 hipError_t launch_batch_finalize(const BatchInst *B, int count, int op, int kind, hipStream_t st);
-int64_t backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz);
+// resident workgroups of the persistent kernels on the current device
+hipError_t batch_persistent_grids(int &fwd, int &bwd, int &dir);
+hipError_t batch_backward_occupancy(int &per_cu);
+hipError_t batch_dir_occupancy(int &per_cu);
+// a single backprojection (plain epilogue) with one of the batched form's variants (tuner)
+hipError_t launch_backward_variant(const GeoDev &g, int variant, const float *proj, float *out, hipStream_t st);
+int64_t backward_variant_grid(const GeoDev &g, int variant, int &nbx, int &nby, int &nbz);
+int backward_default_variant(const GeoDev &g);
 int64_t tt_backward_grid_dims(const GeoDev &g, int &nbx, int &nby, int &nbz);
 
 }  // namespace kct

@@ -214,27 +214,56 @@ hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_
     return hipGetLastError();
 }
 
-// Batched p = A d with |p|^2 partials for every instance (CGLS steps of a
-// batched solve); each instance uses its own rows-per-lane variant.
-__global__ __launch_bounds__(256) void kb_forward(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
-                                                  int count)
+// Persistent batched p = A d with |p|^2 partials for every instance (CGLS
+// steps of a batched solve): every workgroup takes items from the queue until
+// it is empty; an item is up to BATCH_ITEM_FWD workgroup tiles of one
+// instance's forward grid, in its own rows-per-lane variant.
+__global__ __launch_bounds__(256) void kp_forward(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
+                                                  int count, BatchQueue *__restrict__ q)
 {
-    const int64_t w = blockIdx.x;
-    const int i = batch_find(off, count, w);
-    const BatchInst *bi = B + i;
-    if (bi->sc->done) return;
-    const int64_t lw = w - off[i];
-    if (lw >= fwd_grid(bi->g, bi->fwd_r).nblocks) return;  // padding of the instance's grid
-    if (bi->fwd_r == 1)
-        forward_block<float, float, FWD_NORM, 1>(bi->g, lw, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
-    else
-        forward_block<float, float, FWD_NORM, 2>(bi->g, lw, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
+    const int64_t total = off[count];
+    for (;;) {
+        const int64_t item = batch_pop(q);
+        if (item >= total) break;
+        const int i = batch_find(off, count, item);
+        const BatchInst *bi = B + i;
+        if (bi->sc->done) continue;
+        const int64_t t0 = (item - off[i]) * BATCH_ITEM_FWD;
+        const int64_t t1 = t0 + BATCH_ITEM_FWD < bi->nf ? t0 + BATCH_ITEM_FWD : bi->nf;
+        for (int64_t t = t0; t < t1; ++t) {
+            if (bi->fwd_r == 1)
+                forward_block<float, float, FWD_NORM, 1>(bi->g, t, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
+            else
+                forward_block<float, float, FWD_NORM, 2>(bi->g, t, bi->d, bi->dz, bi->p, nullptr, bi->sc, bi->part);
+            __syncthreads();  // the tile's block sum is read before the next tile writes it
+        }
+    }
+    batch_exit(q);
 }
 
-hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, int64_t blocks, hipStream_t st)
+hipError_t launch_batch_forward(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid,
+                                hipStream_t st)
 {
-    hipLaunchKernelGGL(kb_forward, dim3((unsigned)blocks), dim3(256), 0, st, B, off, count);
+    hipLaunchKernelGGL(kp_forward, dim3((unsigned)grid), dim3(256), 0, st, B, off, count, q);
     return hipGetLastError();
+}
+
+// Resident workgroups of the persistent batched kernels: the device's compute
+// units times the workgroups one of them holds.
+hipError_t batch_persistent_grids(int &fwd, int &bwd, int &dir)
+{
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int nf = 0, nb = 0, nd = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nf, kp_forward, 256, 0);
+    if (e == hipSuccess) e = batch_backward_occupancy(nb);
+    if (e == hipSuccess) e = batch_dir_occupancy(nd);
+    if (e != hipSuccess) return e;
+    fwd = cus * (nf > 0 ? nf : 1);
+    bwd = cus * (nb > 0 ? nb : 1);
+    dir = cus * (nd > 0 ? nd : 1);
+    return hipSuccess;
 }
 
 #define KCT_INST(TV, TP)                                                                                       \

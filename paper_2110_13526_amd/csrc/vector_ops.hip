@@ -208,6 +208,7 @@ __device__ __forceinline__ void finalize_step(Scalars *__restrict__ sc, const do
         sc->done = 1;
         sc->stop = reason;
         sc->skip_bwd = 1;
+        sc->t_done = wall_clock64();  // the solve's completion time on the device clock
     };
     switch (op) {
     case F_NB0:  // NB0 = |b|
@@ -369,6 +370,7 @@ __global__ __launch_bounds__(TB) void kb_vec(const BatchInst *__restrict__ B, in
             s.err = err;
             s.sr = s.sp = s.sw = 1.0;
             s.fwd_scale = s.bwd_scale = 1.0f;
+            s.t_start = wall_clock64();
             *sc = s;
         }
         return;
@@ -406,19 +408,35 @@ __global__ __launch_bounds__(TB) void kb_vec(const BatchInst *__restrict__ B, in
     }
 }
 
+// Persistent batched d = r + beta d with its z-fastest copy: every workgroup
+// takes items from the queue until it is empty; an item is up to
+// BATCH_ITEM_DIR 32 x 32 tiles of one instance (tile numbering of k_cgls_d).
 template <int FIRST>
-__global__ __launch_bounds__(TB) void kb_dir(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
-                                             int count)
+__global__ __launch_bounds__(TB) void kp_dir(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
+                                             int count, BatchQueue *__restrict__ q)
 {
-    const int64_t w = blockIdx.x;
-    const int i = batch_find(off, count, w);
-    const BatchInst *bi = B + i;
-    if (bi->sc->done) return;
-    const int gx = (bi->g.nx + 31) / 32, gz = (bi->g.nz + 31) / 32;
-    const int64_t lw = w - off[i];
-    if (lw >= (int64_t)gx * gz * bi->g.ny) return;
-    cgls_d_tile<float, FIRST>(bi->g.nx, bi->g.ny, bi->g.nz, bi->r, bi->d, bi->dz, bi->sc, nullptr, (int)(lw % gx),
-                              (int)((lw / gx) % gz), (int)(lw / ((int64_t)gx * gz)), lw);
+    const int64_t total = off[count];
+    for (;;) {
+        const int64_t item = batch_pop(q);
+        if (item >= total) break;
+        const int i = batch_find(off, count, item);
+        const BatchInst *bi = B + i;
+        if (bi->sc->done) continue;
+        const int gx = (bi->g.nx + 31) / 32, gz = (bi->g.nz + 31) / 32;
+        const int64_t t0 = (item - off[i]) * BATCH_ITEM_DIR;
+        const int64_t t1 = t0 + BATCH_ITEM_DIR < bi->ndir ? t0 + BATCH_ITEM_DIR : bi->ndir;
+        for (int64_t t = t0; t < t1; ++t) {
+            cgls_d_tile<float, FIRST>(bi->g.nx, bi->g.ny, bi->g.nz, bi->r, bi->d, bi->dz, bi->sc, nullptr,
+                                      (int)(t % gx), (int)((t / gx) % gz), (int)(t / ((int64_t)gx * gz)), t);
+            __syncthreads();  // the LDS tile is read before the next tile writes it
+        }
+    }
+    batch_exit(q);
+}
+
+hipError_t batch_dir_occupancy(int &per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kp_dir<0>, TB, 0);
 }
 
 __global__ __launch_bounds__(TB) void kb_finalize(const BatchInst *__restrict__ B, int op, int kind)
@@ -434,11 +452,11 @@ hipError_t launch_batch_vec(const BatchInst *B, int count, int op, int maxiter, 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, int64_t blocks, int first,
+hipError_t launch_batch_dir(const BatchInst *B, const int64_t *off, int count, BatchQueue *q, int grid, int first,
                             hipStream_t st)
 {
-    if (first) hipLaunchKernelGGL(kb_dir<1>, dim3((unsigned)blocks), dim3(TB), 0, st, B, off, count);
-    else hipLaunchKernelGGL(kb_dir<0>, dim3((unsigned)blocks), dim3(TB), 0, st, B, off, count);
+    if (first) hipLaunchKernelGGL(kp_dir<1>, dim3((unsigned)grid), dim3(TB), 0, st, B, off, count, q);
+    else hipLaunchKernelGGL(kp_dir<0>, dim3((unsigned)grid), dim3(TB), 0, st, B, off, count, q);
     return hipGetLastError();
 }
 

@@ -1,12 +1,14 @@
 """Batched form: many independent CGLS reconstructions with their own
-geometries in one launch per step, with the iteration replayed as a HIP graph,
+geometries, one launch per step for all instances (persistent work-queue
+launches for the projector steps), the iteration replayed as a HIP graph,
 through the C ABI (kct_batch_*).
 
-Each instance keeps its own scalars and the block decomposition of its own
-solve, so with the same forward variant a batched solve returns exactly the bits
-of the instance's separate kct_cgls_solve; graph replay and plain launches give
-the same bits; the tuner may change an instance's forward variant, which only
-regroups the partial sums of |p|^2 (results within the FP32 solver bound).
+Each instance keeps its own scalars and the tile decomposition of its own
+solve, so with the default variants a batched solve returns exactly the bits of
+the instance's separate kct_cgls_solve; graph replay and plain launches give
+the same bits; the tuner may change an instance's forward or backprojection
+variant, which only regroups partial sums (results within the FP32 solver
+bound).
 """
 import json
 import os
@@ -85,7 +87,7 @@ def test_batch_tuner_and_cache(small_batch, tmp_path):
     lines = open(cache).read().split("\n")
     keys = {ln.split()[0] for ln in lines if ln.strip()}
     assert len(keys) == len({(g.nx, g.ny, g.nz, g.n_views, g.nv, g.nu) for g, _, _ in probs})
-    assert all(ln.split()[1] in ("1", "2") for ln in lines if ln.strip())
+    assert all(ln.split()[1] in ("1", "2") and ln.split()[2] in ("0", "1") for ln in lines if ln.strip())
     xs, infos = batch.cgls(bs, K)
     for x, r in zip(xs, ref):
         assert rel(to_np(x), to_np(r)) < 1e-5
@@ -95,6 +97,27 @@ def test_batch_tuner_and_cache(small_batch, tmp_path):
     assert open(cache).read().split("\n") == lines
     batch.close()
     batch2.close()
+
+
+def test_batch_latencies(small_batch):
+    """Per-instance completion times of a batched solve, on the device clock:
+    positive, within the solve's wall time, and read again unchanged."""
+    import paper_2110_13526_amd as kct
+    torch = torch_mod()
+    probs, geoms, bs = small_batch
+    batch = kct.Batch(geoms)
+    with pytest.raises(kct.KctError):
+        batch.latencies()  # no solve yet
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch.cgls(bs, 6)
+    wall = time.perf_counter() - t
+    lat = batch.latencies()
+    say(f"[batch] latencies {['%.4f' % v for v in lat]} s, wall {wall:.4f} s")
+    assert len(lat) == len(geoms)
+    assert all(0.0 < v <= wall for v in lat)
+    assert batch.latencies() == lat
+    batch.close()
 
 
 def test_batch_zero_iterations_returns_zeros(small_batch):
@@ -168,18 +191,18 @@ def test_batch_c4_full_size():
     batch.close()
 
 
-@pytest.mark.skipif(not os.environ.get("KCT_BATCH_REPORT"),
-                    reason="report run (set KCT_BATCH_REPORT=1): 48 instances of up to 192^3")
 def test_batch_report_c4():
     """The batched workload: 48 seeded instances (64^3..192^3, 60-360 views,
     96^2..288^2 detectors, SID 400-700 mm, SDD 800-1400 mm), CGLS 20 iterations
-    each, FP32.  Reports the batched solve (tuned, graph replay) against the 48
-    separate solves: per-instance latency p50/p99 of the separate solves, the
-    batch's wall time (every instance's latency inside the batch) and the
-    aggregate throughput of both."""
+    each, FP32.  The batched solve (tuned, graph replay) against the 48 separate
+    solves one after another: per-instance latency inside the batch (device
+    clock) and of the separate solves, p50 / p99, aggregate throughput, and the
+    reconstruction error of both.  The batch must beat the separate solves at
+    equal reconstruction error (median error against the phantoms within 1 %)."""
     import paper_2110_13526_amd as kct
     torch = torch_mod()
     K = 20
+    say("[batch] c4 report: building 48 instances")
     probs = [_problem(i, 1.0, torch, oracle_data=False) for i in range(48)]
     geoms = [geometry(g) for g, _, _ in probs]
     bs = [torch.from_numpy(b).to(dev()) for _, _, b in probs]
@@ -187,30 +210,41 @@ def test_batch_report_c4():
     t = time.perf_counter()
     batch.tune()
     t_tune = time.perf_counter() - t
-    batch.cgls(bs, 2)  # warm-up
+    batch.cgls(bs, 2)  # warm-up (records the graph)
     torch.cuda.synchronize()
     t = time.perf_counter()
     xs, infos = batch.cgls(bs, K, graph=True)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t
+    lat_b = np.array(batch.latencies())
+    errs_b = [rel(to_np(x), x_true) for x, (_, x_true, _) in zip(xs, probs)]
     # separate solves, one after another (each one's latency)
     lat = []
+    errs_s = []
     for G, b in zip(geoms, bs):
         kct.cgls(G, b, 1)
     torch.cuda.synchronize()
-    for G, b in zip(geoms, bs):
+    for (g, x_true, _), G, b in zip(probs, geoms, bs):
         t = time.perf_counter()
-        kct.cgls(G, b, K)
+        x, _ = kct.cgls(G, b, K)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t)
+        errs_s.append(rel(to_np(x), x_true))
     lat = np.array(lat)
-    errs = [rel(to_np(x), x_true) for x, (_, x_true, _) in zip(xs, probs)]
     rep = {"instances": 48, "iterations": K, "batched_wall_s": t_batch, "tune_s": t_tune,
+           "batched_latency_p50_s": float(np.percentile(lat_b, 50)),
+           "batched_latency_p99_s": float(np.percentile(lat_b, 99)),
            "batched_instances_per_s": 48 / t_batch, "batched_iterations_per_s": 48 * K / t_batch,
            "separate_total_s": float(lat.sum()), "separate_p50_s": float(np.percentile(lat, 50)),
            "separate_p99_s": float(np.percentile(lat, 99)), "separate_instances_per_s": 48 / float(lat.sum()),
            "speedup_aggregate": float(lat.sum()) / t_batch,
            "voxels_total": int(sum(g.n_vox for g, _, _ in probs)), "rays_total": int(sum(g.n_rays for g, _, _ in probs)),
-           "rel_error_vs_phantom_median": float(np.median(errs))}
+           "rel_error_vs_phantom_median_batched": float(np.median(errs_b)),
+           "rel_error_vs_phantom_median_separate": float(np.median(errs_s)),
+           "rel_error_max_ratio_batched_to_separate": float(max(b / s for b, s in zip(errs_b, errs_s)))}
     say("[batch] c4 " + json.dumps(rep))
     assert all(i.iterations == K for i in infos)
+    assert rep["speedup_aggregate"] > 1.0
+    assert abs(rep["rel_error_vs_phantom_median_batched"] / rep["rel_error_vs_phantom_median_separate"] - 1) <= 0.01
+    assert np.all(lat_b > 0) and np.all(lat_b <= t_batch)
+    batch.close()
