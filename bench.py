@@ -36,9 +36,9 @@ HBM_PEAK_GBS = 8000.0
 # profiles/ is valid only for the sources it was taken with.
 KERNEL_SOURCES = {
     "forward": ("csrc/projector.hip", "csrc/kct_ray.h", "csrc/kct_weights.h", "csrc/kct_internal.h",
-                "csrc/kct_epilogue.h", "build.py"),
+                "csrc/kct_epilogue.h", "csrc/kct_batch.h", "csrc/geometry.cpp", "build.py"),
     "backward": ("csrc/backproject.hip", "csrc/kct_gather.h", "csrc/kct_weights.h", "csrc/kct_internal.h",
-                 "csrc/kct_epilogue.h", "build.py"),
+                 "csrc/kct_epilogue.h", "csrc/kct_batch.h", "csrc/geometry.cpp", "build.py"),
 }
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "projector_c3_hbm_counters.json")
 

@@ -98,9 +98,11 @@ typedef struct kct_geometry_s *kct_geometry;
 
 /* Validate the description and upload the per-view / per-column / per-row ray
  * tables (computed in double precision on the host and rounded once to single).
- * Errors: KCT_ERR_INVALID_ARG for non-positive sizes or pitches, SDD <= SID, or
- * a volume that is not strictly between source and detector; KCT_ERR_HIP if the
- * upload fails.  Synchronous. */
+ * Errors: KCT_ERR_INVALID_ARG for non-positive sizes or pitches, SDD <= SID, a
+ * volume that is not strictly between source and detector, a volume of 2^31
+ * voxels or more (or a side above 2^20), projection data of 2^31 rays or more,
+ * or a detector of 2^28 pixels or more; KCT_ERR_HIP if the upload fails.
+ * Synchronous. */
 kct_status kct_geometry_create(const kct_volume_desc *vol, const kct_cone_desc *cone, kct_geometry *out);
 
 /* Free the tables (NULL is ignored).  The caller must ensure no enqueued work

@@ -32,6 +32,12 @@ __device__ __forceinline__ double bwd_block_sum(double v)
     return r;
 }
 
+// The element of type E at byte offset off from base.
+template <typename E> __device__ __forceinline__ const E *byte_at(const void *base, unsigned off)
+{
+    return reinterpret_cast<const E *>(static_cast<const char *>(base) + off);
+}
+
 // backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
 // backprojection into one volume; its partial sum goes to partials[w].
 // s_pix / s_col: LDS for CH_ROWS x CHC staged pixels and CHC columns.
@@ -104,15 +110,18 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                     int r = (int)(((float)threadIdx.x + 0.5f) * rn), c = (int)threadIdx.x - r * ncol;
                     const int dr = 256 / ncol, dc = 256 - dr * ncol;
                     for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
-                        // the projection value first: its load overlaps the parameter loads
-                        // (offsets within one view fit in 32 bits: a projection has < 2^31 rays)
-                        const A ev = SQ ? (A)0 : to_acc(pk[(unsigned)((cv0 + r) * g.nu + cu0 + c)]);
-                        const ColParam cp = ck[cu0 + c];
-                        const RowParam rp = g.rows[cv0 + r];
+                        // the projection value first: its load overlaps the parameter loads.
+                        // All three are addressed as a uniform base plus a 32-bit byte offset
+                        // (one view's projection values span < 2^31 bytes: a detector has
+                        // < 2^28 pixels)
+                        const unsigned pix = (unsigned)(cv0 + r) * (unsigned)g.nu + (unsigned)(cu0 + c);
+                        const A ev = SQ ? (A)0 : to_acc(*byte_at<T>(pk, pix * (unsigned)sizeof(T)));
+                        const ColParam cp = *byte_at<ColParam>(ck, (unsigned)(cu0 + c) * (unsigned)sizeof(ColParam));
+                        const RowParam rp = *byte_at<RowParam>(g.rows, (unsigned)(cv0 + r) * (unsigned)sizeof(RowParam));
                         const bool par = rp.inv_qz == 0.0f;
                         PixStage<A> ps;
                         ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
-                        ps.czr = zeta_inv_slope(par ? INFINITY : rp.inv_qz, cp.kz);
+                        ps.czr = par ? PAR_INV : zeta_inv_slope(rp.inv_qz, cp.kz);
                         const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
                         ps.le = SQ ? L * L : L * ev;
                         s_pix[r * CHC + c] = ps;
@@ -124,15 +133,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                         }
                     }
                 }
-                if (threadIdx.x < ncol) {
-                    const ColParam cp = ck[cu0 + threadIdx.x];
-                    ColStage cs;
-                    cs.eta_c = cp.eta_c;
-                    cs.inv_a = cp.inv_a;
-                    cs.tcv = cp.tcv;
-                    cs.gz = cp.gp * g.inv_vz;
-                    s_col[threadIdx.x] = cs;
-                }
+                if (threadIdx.x < ncol) s_col[threadIdx.x] = stage_column(g, vp.dom, ck[cu0 + threadIdx.x]);
                 __syncthreads();
                 // 3. gather
                 if (valid) gather_chunk<A, SQ, CHC>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward
 {
     if (skip && *skip) return;
     constexpr int CHC = ch_cols(TZB);
-    __shared__ PixStage<acc_t<T>> s_pix[CH_ROWS * CHC];
+    __shared__ PixStage<acc_t<T>> s_pix[CH_ROWS * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<T, EPI, TZB, CHC>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
                                      s_col);
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(256, 6) void kp_backward(const BatchInst *__restric
                                                       const int64_t *__restrict__ off, int count,
                                                       BatchQueue *__restrict__ q)
 {
-    __shared__ PixStage<float> s_pix[CH_ROWS * VARIANT_LDS_COLS];
+    __shared__ PixStage<float> s_pix[CH_ROWS * VARIANT_LDS_COLS + NH - 1];
     __shared__ ColStage s_col[VARIANT_LDS_COLS];
     const int64_t total = off[count];
     for (;;) {
@@ -262,7 +263,7 @@ template <int TZB, int CHC>
 __global__ __launch_bounds__(256, 6) void k_backward_v(GeoDev g, const float *__restrict__ proj,
                                                        float *__restrict__ out, int nbx, int nby, int nbz)
 {
-    __shared__ PixStage<float> s_pix[CH_ROWS * CHC];
+    __shared__ PixStage<float> s_pix[CH_ROWS * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<float, BWD_PLAIN, TZB, CHC>(g, blockIdx.x, proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
                                                nullptr, s_pix, s_col);

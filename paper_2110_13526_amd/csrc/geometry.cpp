@@ -24,6 +24,8 @@ std::string validate_geometry(const kct_volume_desc &v, const kct_cone_desc &c)
     if (!std::isfinite(v.cx) || !std::isfinite(v.cy) || !std::isfinite(v.cz)) return "volume centre not finite";
     if (c.n_views <= 0 || c.nu <= 0 || c.nv <= 0) return "view and detector counts must be positive";
     if ((int64_t)c.n_views * c.nu * c.nv >= (int64_t)1 << 31) return "projection data has 2^31 rays or more";
+    // the backprojector addresses one view's projection values by 32-bit byte offsets
+    if ((int64_t)c.nu * c.nv >= (int64_t)1 << 28) return "detector has 2^28 pixels or more";
     if (!finite_pos(c.du) || !finite_pos(c.dv)) return "pixel pitch must be positive";
     if (!finite_pos(c.sid) || !finite_pos(c.sdd)) return "SID and SDD must be positive";
     if (!(c.sdd > c.sid)) return "SDD must exceed SID";

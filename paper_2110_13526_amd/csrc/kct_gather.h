@@ -36,16 +36,23 @@ __host__ __device__ constexpr int ch_cols(int tzb) { return tzb == TZ_DEEP ? 32 
 constexpr int NH = 2;                      // detector columns held in registers at once
 
 struct ColStage {  // per staged detector column: in-plane ray parameters
-    float eta_c, inv_a, tcv;
+    float eta_c, inv_a, tcv;  // ColParam's; columns parallel to the eta planes staged as below (PAR_INV)
     float gz;      // d T / d xi with T = (segment fraction) / vz
 };
 
+// Rays parallel to a family of planes are staged as if they crossed them at a
+// slope of PAR_INV, with their coordinate on that axis moved to the middle of
+// the cell they lie in: every plane is then crossed at least PAR_INV / 2 from
+// the origin, far outside any xi-interval (finite, so the two crossings of a
+// cell never give inf - inf), and the general crossing formula gives exactly
+// the parallel-ray intervals of kct_weights.h: everything inside the ray's
+// cell, nothing elsewhere.  Staged records and columns therefore need no
+// parallel case.
+constexpr float PAR_INV = 1.0e30f;
+
 // Per staged pixel.  zc and czr are zeta at xi = 0 and d xi / d zeta of the
-// pixel's ray (zeta_centre and zeta_inv_slope of its row and column).  A row
-// whose rays are parallel to the z-planes (qz == 0) is staged with czr = +inf
-// and zc moved to the middle of the z-cell those rays lie in: the crossings of
-// every z-plane are then +-inf and the general formula gives exactly the
-// parallel-ray weights of kct_weights.h.
+// pixel's ray (zeta_centre and zeta_inv_slope of its row and column); rows
+// whose rays are parallel to the z-planes (qz == 0) staged as above.
 template <typename A> struct PixStage {
     float zc, czr;
     A le;          // L * e, in the accumulator precision
@@ -108,16 +115,30 @@ __host__ __device__ __forceinline__ void voxel_columns(const GeoDev &g, const Vi
     ub = (int)floorf(fc + hc);
 }
 
-// xi-interval [lo, hi] in which the rays of a detector column cross the voxel
-// column whose xi-cell starts at lo_xi and whose eta-cell is ieta (empty when
-// hi <= lo).
+// xi-interval [lo, hi] in which the rays of a staged detector column cross the
+// voxel column whose xi-cell starts at lo_xi and whose eta-cell is ieta (empty
+// when hi <= lo): cell_range of kct_weights.h without its parallel case, which
+// the staging removed (PAR_INV).
 __host__ __device__ __forceinline__ void column_interval(const ColStage &cs, float lo_xi, int ieta, float heta,
                                                          float &lo, float &hi)
 {
-    float lo_e, hi_e;
-    cell_range(ieta, heta, cs.eta_c, cs.inv_a, lo_e, hi_e);
-    lo = fmaxf(lo_xi, lo_e);
-    hi = fminf(lo_xi + 1.0f, hi_e);
+    const float mb = (float)ieta - heta;
+    const float b0 = cross_at(mb, cs.eta_c, cs.inv_a), b1 = cross_at(mb + 1.0f, cs.eta_c, cs.inv_a);
+    lo = fmaxf(lo_xi, fminf(b0, b1));
+    hi = fminf(lo_xi + 1.0f, fmaxf(b0, b1));
+}
+
+// The staged form of a detector column (view with in-plane domain dom).
+__host__ __device__ __forceinline__ ColStage stage_column(const GeoDev &g, int dom, const ColParam &cp)
+{
+    ColStage cs;
+    const bool par = cp.inv_a == 0.0f;
+    const float heta = dom == 0 ? g.hy : g.hx;
+    cs.eta_c = par ? ((float)parallel_cell(cp.eta_c, heta) - heta) + 0.5f : cp.eta_c;
+    cs.inv_a = par ? PAR_INV : cp.inv_a;
+    cs.tcv = cp.tcv;
+    cs.gz = cp.gp * g.inv_vz;
+    return cs;
 }
 
 // One staged record, read as a whole (one 128-bit LDS read).
@@ -135,27 +156,112 @@ template <> __host__ __device__ __forceinline__ PixStage<float> load_pix<float>(
 
 // The candidates of one detector row for one voxel: the rays of the row in the
 // nh (<= NH) staged hit columns starting at prow, whose in-plane xi-intervals
-// are [lo[h], hi[h]], against the voxel's z-planes mb and mb1.  Returns
-// a + sum of w * (L e) (w^2 * le when SQ).
+// are [lo[h], hi[h]] with lo[h] <= hi[h], against the voxel's z-planes mb and
+// mb1.  Returns a + sum of w * (L e) (w^2 * le when SQ).  All NH records are
+// read before the first is used (one wait for both); the staging buffer holds
+// a spare record past its last, so prow + NH - 1 is always inside it.
 template <typename A, bool SQ>
 __host__ __device__ __forceinline__ A add_row(const PixStage<A> *prow, int nh, const float (&lo)[NH],
                                               const float (&hi)[NH], float mb, float mb1, A a)
 {
+    PixStage<A> p[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) p[h] = load_pix(prow + h);
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
         if (h == 0 || h < nh) {
-            const PixStage<A> p = load_pix(prow + h);
-            const float b0 = cross_at(mb, p.zc, p.czr), b1 = cross_at(mb1, p.zc, p.czr);
+            const float b0 = cross_at(mb, p[h].zc, p[h].czr), b1 = cross_at(mb1, p[h].zc, p[h].czr);
+            // With lo <= hi, med3(hi, b0, b1) - med3(lo, b0, b1) is the overlap
             // min(hi, max(b0, b1)) - max(lo, min(b0, b1)) wherever that is positive
-            // (there hi > min(b0, b1) and lo < max(b0, b1), so clamping hi and lo to
-            // [min, max] selects the same operands); elsewhere <= 0 like it.  Clamped
-            // at 0, a candidate that misses adds w * le = 0 and leaves the sum as it
-            // is (le is finite), so no compare and select are needed.
-            const float w = fmaxf(med3f(hi[h], b0, b1) - med3f(lo[h], b0, b1), 0.0f);
-            a = fma_acc(SQ ? w * w : w, p.le, a);
+            // (both medians then pick those operands) and exactly 0 elsewhere (both
+            // medians clamp to the same end of [min, max], or hi = lo): a candidate
+            // that misses adds 0 * le = 0 (le is finite) and leaves the sum as it is.
+            const float w = med3f(hi[h], b0, b1) - med3f(lo[h], b0, b1);
+            a = fma_acc(SQ ? w * w : w, p[h].le, a);
         }
     }
     return a;
+}
+
+// pg + r * CHC for a pointer pg into the LDS staging buffer: on the GPU one
+// shift-and-add of the 32-bit LDS address when a row of records spans a power
+// of two bytes.
+template <typename A, int CHC>
+__host__ __device__ __forceinline__ const PixStage<A> *row_record(const PixStage<A> *pg, int r)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    constexpr unsigned row_bytes = CHC * sizeof(PixStage<A>);
+    if constexpr ((row_bytes & (row_bytes - 1)) == 0) {
+        typedef const __attribute__((address_space(3))) PixStage<A> *lds_rec;
+        const unsigned base = (unsigned)(size_t)(lds_rec)pg;
+        unsigned addr;
+        asm("v_lshl_add_u32 %0, %1, %3, %2" : "=v"(addr) : "v"(r), "v"(base), "i"(__builtin_ctz(row_bytes)));
+        return (const PixStage<A> *)(lds_rec)(size_t)addr;
+    }
+#endif
+    return pg + r * CHC;
+}
+
+// Whether pred holds in every active lane of the wavefront (on a CPU build: in
+// the one lane).
+__host__ __device__ __forceinline__ bool wave_all(bool pred)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __all(pred);
+#else
+    return pred;
+#endif
+}
+
+// The voxels of one lane for one group of hit columns: voxel j (j < nzb) has
+// the planes mbz0 + j and mbz0 + j + 1 and the candidate rows va1 + 1 .. vb with
+// va1 = floor(l0 + j sl) and vb = floor(h0 + (j + 1) sh), clamped to the staged
+// rows (vlow = first staged row - 1, vmax = last) when clamp (uniform over the
+// wavefront: a scalar branch around the two clamps).  pg + va1 * CHC is the
+// record of row va1 + 1 in the group's first column.
+template <typename A, bool SQ, int CHC, int TZN>
+__host__ __device__ __forceinline__ void voxel_rows(const PixStage<A> *pg, int nh, const float (&lo)[NH],
+                                                    const float (&hi)[NH], float mbz0, int nzb, float l0, float sl,
+                                                    float h0, float sh, bool clamp, int vlow, int vmax,
+                                                    A (&acc)[TZN])
+{
+    // The per-voxel plane values do not depend on the column group; computed
+    // here they stay short-lived (hoisted out of the group loop, all TZ of them
+    // would stay live through it).  The empty asm keeps the compiler from
+    // hoisting them.
+    float mbb = mbz0;
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(mbb));
+#endif
+    float mb = mbb;  // lower plane of voxel j (exact: an integer or half-integer)
+#pragma unroll
+    for (int j = 0; j < TZN; ++j) {
+        const float mb1 = mb + 1.0f;
+        if (j < nzb) {
+            // candidate rows va1 + 1 .. vb: floor(lo) + 1 is ceil(lo) except at an
+            // integer lo, whose row lies 0.01 below the true bound and is rightly left out
+            const float vlo = __builtin_fmaf((float)j, sl, l0), vhi = __builtin_fmaf((float)(j + 1), sh, h0);
+            int va1 = (int)floorf(vlo), vb = (int)floorf(vhi);
+            if (clamp) {
+#if defined(__HIP_DEVICE_COMPILE__)
+                asm volatile("");  // keeps the branch (not two selects)
+#endif
+                va1 = va1 < vlow ? vlow : va1;
+                vb = vb > vmax ? vmax : vb;
+            }
+            if (va1 < vb) {
+                // the first candidate row outside the loop: most voxels have one
+                const PixStage<A> *prow = row_record<A, CHC>(pg, va1);
+                A a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, acc[j]);
+                for (int v = va1 + 2; v <= vb; ++v) {
+                    prow += CHC;
+                    a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, a);
+                }
+                acc[j] = a;
+            }
+        }
+        mb = mb1;
+    }
 }
 
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
@@ -210,6 +316,7 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
                 tmin = fminf(tmin, fminf(T1, T2));
                 tmax = fmaxf(tmax, fmaxf(T1, T2));
             }
+            hi[h] = fmaxf(hi[h], lo[h]);  // an empty interval becomes [lo, lo]: its weights are 0 (add_row)
         }
         if (!(tmax > 0.0f)) continue;  // no column of this group is hit
         // Rows: inside these columns a ray of row height qz meets the z-cell with
@@ -228,39 +335,14 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         const float sl = (fminf(b1, b2) - fminf(a1, a2)) * inv_nzb;
         const float sh = (fmaxf(b1, b2) - fmaxf(a1, a2)) * inv_nzb;
         const float l0 = fminf(a1, a2) + vofs_lo, h0 = fmaxf(a1, a2) + vofs_hi;
-        // The per-voxel plane values below do not depend on the column group;
-        // computed here they stay short-lived (hoisted out of the group loop,
-        // all TZ of them would stay live through it).  The empty asm keeps the
-        // compiler from hoisting them.
-        float mbb = mbz0;
-#if defined(__HIP_DEVICE_COMPILE__)
-        asm volatile("" : "+v"(mbb));
-#endif
-        float mb = mbb;  // lower plane of voxel j (exact: an integer or half-integer)
-        const int gofs = (c0 - cu0) + (1 - cv0) * CHC;  // record of row va1 + 1 at va1 * CHC + gofs
-#pragma unroll
-        for (int j = 0; j < TZN; ++j) {
-            const float mb1 = mb + 1.0f;
-            if (j < nzb) {
-                // candidate rows va1 + 1 .. vb: floor(lo) + 1 is ceil(lo) except at an
-                // integer lo, whose row lies 0.01 below the true bound and is rightly left out
-                const float vlo = __builtin_fmaf((float)j, sl, l0), vhi = __builtin_fmaf((float)(j + 1), sh, h0);
-                int va1 = (int)floorf(vlo), vb = (int)floorf(vhi);
-                va1 = va1 < cv0 - 1 ? cv0 - 1 : va1;
-                vb = vb > vmax ? vmax : vb;
-                if (va1 < vb) {
-                    // the first candidate row outside the loop: most voxels have one
-                    const PixStage<A> *prow = s_pix + (va1 * CHC + gofs);
-                    A a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, acc[j]);
-                    for (int v = va1 + 2; v <= vb; ++v) {
-                        prow += CHC;
-                        a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, a);
-                    }
-                    acc[j] = a;
-                }
-            }
-            mb = mb1;
-        }
+        // Every lane's candidate rows lie in the staged chunk when its lowest
+        // (voxel 0) and highest (voxel nzb - 1) bounds do: l0 + j sl and h0 + j sh
+        // do not decrease with j (sl, sh >= 0: the plane heights in row units grow
+        // with z, and fused multiply-adds round monotonically).  A wavefront whose
+        // lanes all pass skips the clamps.
+        const bool inside = l0 >= (float)(cv0 - 1) && __builtin_fmaf((float)nzb, sh, h0) < (float)(vmax + 1);
+        const PixStage<A> *pg = s_pix + ((c0 - cu0) + (1 - cv0) * CHC);  // row va1 + 1 at pg + va1 * CHC
+        voxel_rows<A, SQ, CHC, TZN>(pg, nh, lo, hi, mbz0, nzb, l0, sl, h0, sh, !wave_all(inside), cv0 - 1, vmax, acc);
     }
 }
 

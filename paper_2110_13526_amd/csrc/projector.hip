@@ -145,7 +145,7 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
 }
 
 template <typename TV, typename TP, int EPI>
-__global__ __launch_bounds__(256) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+__global__ __launch_bounds__(256, sizeof(acc_t<TV>) != 4 ? 1 : 8) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
                                                  TP *__restrict__ out, const TP *__restrict__ aux,
                                                  const Scalars *__restrict__ sc, double *__restrict__ partials,
                                                  const int *__restrict__ skip)
@@ -218,7 +218,7 @@ hipError_t launch_forward_r(const GeoDev &g, const float *vol, const float *vol_
 // steps of a batched solve): every workgroup takes items from the queue until
 // it is empty; an item is up to BATCH_ITEM_FWD workgroup tiles of one
 // instance's forward grid, in its own rows-per-lane variant.
-__global__ __launch_bounds__(256) void kp_forward(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
+__global__ __launch_bounds__(256, 8) void kp_forward(const BatchInst *__restrict__ B, const int64_t *__restrict__ off,
                                                   int count, BatchQueue *__restrict__ q)
 {
     const int64_t total = off[count];
