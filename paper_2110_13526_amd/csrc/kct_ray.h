@@ -12,6 +12,59 @@
 
 namespace kct {
 
+// v for a value equal in every lane of the wavefront, made visibly uniform on
+// the GPU (a scalar copy), so that addresses built from it stay scalar.
+__host__ __device__ __forceinline__ int uniform_int(int v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_readfirstlane(v);
+#else
+    return v;
+#endif
+}
+
+// Element m of a z-column (element 0 when !ok: it exists, and the caller
+// discards the value).  ZCol<T, 1> is a column of the z-fastest copy: on the
+// GPU a buffer resource over the column's nz elements (built in scalar
+// registers from the column's base, which is equal in every lane of the
+// wavefront), so each load takes a 32-bit per-lane byte offset and no 64-bit
+// address arithmetic; a read beyond the column returns 0.  ZCol<T, 0> is a
+// column of the z-slowest layout (stride sz), read through its pointer.
+template <typename T, int SZ> struct ZCol {
+    const T *col;
+    int sz;
+    __host__ __device__ __forceinline__ ZCol(const T *c, int, int s) : col(c), sz(s) {}
+    __host__ __device__ __forceinline__ T at(bool ok, int m) const { return col[ok ? (unsigned)m * (unsigned)sz : 0u]; }
+};
+
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> struct ZCol<T, 1> {
+    __amdgpu_buffer_rsrc_t rsrc;
+    __device__ __forceinline__ ZCol(const T *c, int nz, int)
+        : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(c), (short)0, nz * (int)sizeof(T), 0x00020000))
+    {
+    }
+    __device__ __forceinline__ T at(bool ok, int m) const
+    {
+        const int boff = ok ? m * (int)sizeof(T) : 0;
+        if constexpr (sizeof(T) == 4) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, boff, 0, 0));
+        } else if constexpr (sizeof(T) == 2) {
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, boff, 0, 0));
+        } else {
+            static_assert(sizeof(T) == 8, "4-, 2- or 8-byte storage");
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, boff, 0, 0));
+        }
+    }
+};
+#else
+template <typename T> struct ZCol<T, 1> {
+    const T *col;
+    __host__ __forceinline__ ZCol(const T *c, int, int) : col(c) {}
+    __host__ __forceinline__ T at(bool ok, int m) const { return col[ok ? (unsigned)m : 0u]; }
+};
+#endif
+
 // z-walk state of one ray: current z-cell mz (-1 / nz stand for "below" /
 // "above" the volume), walking direction stz (and as a float, fstz), the
 // index-frame coordinate hbf of the plane where the walk leaves mz (an exact small
@@ -184,7 +237,8 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
     float t0 = t_start;
     for (int guard = nxi + neta + 4; t0 < t_end && guard > 0; --guard) {
         const float t1 = fminf(hx, he);
-        const T *col = vol + base;
+        const T *col = vol + uniform_int(base);
+        const ZCol<T, SZ> zc(col, nz, sz);
         // The current z-cell of every row first, with the R loads issued
         // together (a lane without a contribution reads element 0 of the column,
         // which exists, and keeps its sum), then the z-cells entered inside the
@@ -196,9 +250,8 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             w[r] = fminf(t1, zs[r].hzv) - fmaxf(t0, zs[r].lz);
-            ok[r] = w[r] > 0.0f && (unsigned)zs[r].mz < (unsigned)nz;
-            const unsigned off = !ok[r] ? 0u : (SZ == 1 ? (unsigned)zs[r].mz : (unsigned)zs[r].mz * (unsigned)sz);
-            v[r] = col[off];
+            ok[r] = (w[r] > 0.0f) & ((unsigned)zs[r].mz < (unsigned)nz);
+            v[r] = zc.at(ok[r], zs[r].mz);
         }
         // the first z-plane crossed inside the piece, if any: every lane steps
         // (kept only where the ray crosses) and the R loads again go out together
@@ -218,9 +271,8 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
                 z.hzv = nhzv;
             }
             w2[r] = fminf(t1, z.hzv) - fmaxf(t0, z.lz);
-            ok2[r] = c && w2[r] > 0.0f && (unsigned)z.mz < (unsigned)nz;
-            const unsigned off = !ok2[r] ? 0u : (SZ == 1 ? (unsigned)z.mz : (unsigned)z.mz * (unsigned)sz);
-            v2[r] = col[off];
+            ok2[r] = c & (w2[r] > 0.0f) & ((unsigned)z.mz < (unsigned)nz);
+            v2[r] = zc.at(ok2[r], z.mz);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {

@@ -83,7 +83,8 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
     // (a function of the column) runs on scalar registers and branches
     const int iu = cg * FWD_COLS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = (int)(threadIdx.x & 63);
-    const ViewParam vp = g.views[k];
+    ViewParam vp = g.views[k];
+    vp.dom = __builtin_amdgcn_readfirstlane(vp.dom);  // uniform: the volume's base and strides follow it
 
     int nxi, neta, sxi, seta, sz;
     float hxi, heta;
