@@ -23,18 +23,24 @@ __host__ __device__ __forceinline__ int uniform_int(int v)
 #endif
 }
 
-// Element m of a z-column (element 0 when !ok: it exists, and the caller
-// discards the value).  ZCol<T, 1> is a column of the z-fastest copy: on the
-// GPU a buffer resource over the column's nz elements (built in scalar
-// registers from the column's base, which is equal in every lane of the
-// wavefront), so each load takes a 32-bit per-lane byte offset and no 64-bit
-// address arithmetic; a read beyond the column returns 0.  ZCol<T, 0> is a
-// column of the z-slowest layout (stride sz), read through its pointer.
+// Element m of a z-column as an accumulator value, 0 for m outside [0, nz)
+// (the walk's sentinel cells -1 and nz).  ZCol<T, 1> is a column of the
+// z-fastest copy: on the GPU a buffer resource over the column's nz elements
+// (built in scalar registers from the column's base, which is equal in every
+// lane of the wavefront), so each load takes a 32-bit per-lane byte offset, no
+// 64-bit address arithmetic, and the hardware's range check supplies the 0
+// outside the column.  ZCol<T, 0> is a column of the z-slowest layout (stride
+// sz), read through its pointer.
 template <typename T, int SZ> struct ZCol {
     const T *col;
-    int sz;
-    __host__ __device__ __forceinline__ ZCol(const T *c, int, int s) : col(c), sz(s) {}
-    __host__ __device__ __forceinline__ T at(bool ok, int m) const { return col[ok ? (unsigned)m * (unsigned)sz : 0u]; }
+    int nz, sz;
+    __host__ __device__ __forceinline__ ZCol(const T *c, int n, int s) : col(c), nz(n), sz(s) {}
+    __host__ __device__ __forceinline__ acc_t<T> at(int m) const
+    {
+        const bool in = (unsigned)m < (unsigned)nz;
+        const acc_t<T> v = to_acc(col[in ? (unsigned)m * (unsigned)(SZ == 1 ? 1 : sz) : 0u]);
+        return in ? v : acc_t<T>(0);
+    }
 };
 
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -44,24 +50,18 @@ template <typename T> struct ZCol<T, 1> {
         : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(c), (short)0, nz * (int)sizeof(T), 0x00020000))
     {
     }
-    __device__ __forceinline__ T at(bool ok, int m) const
+    __device__ __forceinline__ acc_t<T> at(int m) const
     {
-        const int boff = ok ? m * (int)sizeof(T) : 0;
+        const int boff = m * (int)sizeof(T);  // m = -1 or nz: beyond the resource, read as 0
         if constexpr (sizeof(T) == 4) {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, boff, 0, 0));
+            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, boff, 0, 0)));
         } else if constexpr (sizeof(T) == 2) {
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, boff, 0, 0));
+            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, boff, 0, 0)));
         } else {
             static_assert(sizeof(T) == 8, "4-, 2- or 8-byte storage");
-            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, boff, 0, 0));
+            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, boff, 0, 0)));
         }
     }
-};
-#else
-template <typename T> struct ZCol<T, 1> {
-    const T *col;
-    __host__ __forceinline__ ZCol(const T *c, int, int) : col(c) {}
-    __host__ __forceinline__ T at(bool ok, int m) const { return col[ok ? (unsigned)m : 0u]; }
 };
 #endif
 
@@ -240,24 +240,21 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
         const T *col = vol + uniform_int(base);
         const ZCol<T, SZ> zc(col, nz, sz);
         // The current z-cell of every row first, with the R loads issued
-        // together (a lane without a contribution reads element 0 of the column,
-        // which exists, and keeps its sum), then the z-cells entered inside the
-        // piece: the same additions in the same order as a walk that handles one
-        // z-cell at a time.
+        // together, then the z-cells entered inside the piece: the same additions
+        // in the same order as a walk that handles one z-cell at a time.  A cell
+        // without a contribution (weight <= 0, or a sentinel cell, read as 0)
+        // adds max(w, 0) * x = 0 and leaves the sum as it is.
         float w[R];
-        bool ok[R];
-        T v[R];
+        acc_t<T> v[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            w[r] = fminf(t1, zs[r].hzv) - fmaxf(t0, zs[r].lz);
-            ok[r] = (w[r] > 0.0f) & ((unsigned)zs[r].mz < (unsigned)nz);
-            v[r] = zc.at(ok[r], zs[r].mz);
+            w[r] = fmaxf(fminf(t1, zs[r].hzv) - fmaxf(t0, zs[r].lz), 0.0f);
+            v[r] = zc.at(zs[r].mz);
         }
         // the first z-plane crossed inside the piece, if any: every lane steps
         // (kept only where the ray crosses) and the R loads again go out together
         float w2[R];
-        bool ok2[R];
-        T v2[R];
+        acc_t<T> v2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             ZWalk &z = zs[r];
@@ -270,16 +267,13 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
                 z.hbf = nhbf;
                 z.hzv = nhzv;
             }
-            w2[r] = fminf(t1, z.hzv) - fmaxf(t0, z.lz);
-            ok2[r] = c & (w2[r] > 0.0f) & ((unsigned)z.mz < (unsigned)nz);
-            v2[r] = zc.at(ok2[r], z.mz);
+            w2[r] = c ? fmaxf(fminf(t1, z.hzv) - fmaxf(t0, z.lz), 0.0f) : 0.0f;
+            v2[r] = zc.at(z.mz);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const acc_t<T> t = fma_acc(w[r], to_acc(v[r]), acc[r]);
-            acc[r] = ok[r] ? t : acc[r];
-            const acc_t<T> t2 = fma_acc(w2[r], to_acc(v2[r]), acc[r]);
-            acc[r] = ok2[r] ? t2 : acc[r];
+            acc[r] = fma_acc(w[r], v[r], acc[r]);
+            acc[r] = fma_acc(w2[r], v2[r], acc[r]);
         }
         // further crossings inside the piece (steep rays only)
 #pragma unroll
