@@ -40,7 +40,8 @@ template <typename E> __device__ __forceinline__ const E *byte_at(const void *ba
 
 // backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
 // backprojection into one volume; its partial sum goes to partials[w].
-// s_pix / s_col: LDS for CH_ROWS x CHC staged pixels and CHC columns.
+// s_pix / s_col: LDS for CH_ROWS x CHC staged pixels (plus two zero rows and a
+// spare record) and CHC columns.
 template <typename T, int EPI, int TZB, int CHC>
 __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *__restrict__ proj,
                                                T *__restrict__ out, T *__restrict__ out_z,
@@ -134,6 +135,17 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                     }
                 }
                 if (threadIdx.x < ncol) s_col[threadIdx.x] = stage_column(g, vp.dom, ck[cu0 + threadIdx.x]);
+                // two zero rows after the chunk's: the gather reads a voxel's first
+                // candidate row without a branch, and these have weight 0 for any voxel
+                if (threadIdx.x < 2 * ncol) {
+                    const int zr = threadIdx.x < ncol ? nrow : nrow + 1;
+                    const int zcol = threadIdx.x < ncol ? (int)threadIdx.x : (int)threadIdx.x - ncol;
+                    PixStage<A> z{};
+                    z.zc = 0.0f;
+                    z.czr = 0.0f;
+                    z.le = (A)0;
+                    s_pix[zr * CHC + zcol] = z;
+                }
                 __syncthreads();
                 // 3. gather
                 if (valid) gather_chunk<A, SQ, CHC>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
@@ -170,7 +182,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward
 {
     if (skip && *skip) return;
     constexpr int CHC = ch_cols(TZB);
-    __shared__ PixStage<acc_t<T>> s_pix[CH_ROWS * CHC + NH - 1];
+    __shared__ PixStage<acc_t<T>> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<T, EPI, TZB, CHC>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
                                      s_col);
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(256, 6) void kp_backward(const BatchInst *__restric
                                                       const int64_t *__restrict__ off, int count,
                                                       BatchQueue *__restrict__ q)
 {
-    __shared__ PixStage<float> s_pix[CH_ROWS * VARIANT_LDS_COLS + NH - 1];
+    __shared__ PixStage<float> s_pix[(CH_ROWS + 2) * VARIANT_LDS_COLS + NH - 1];
     __shared__ ColStage s_col[VARIANT_LDS_COLS];
     const int64_t total = off[count];
     for (;;) {
@@ -263,7 +275,7 @@ template <int TZB, int CHC>
 __global__ __launch_bounds__(256, 6) void k_backward_v(GeoDev g, const float *__restrict__ proj,
                                                        float *__restrict__ out, int nbx, int nby, int nbz)
 {
-    __shared__ PixStage<float> s_pix[CH_ROWS * CHC + NH - 1];
+    __shared__ PixStage<float> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<float, BWD_PLAIN, TZB, CHC>(g, blockIdx.x, proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
                                                nullptr, s_pix, s_col);

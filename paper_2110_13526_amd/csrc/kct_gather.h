@@ -158,8 +158,8 @@ template <> __host__ __device__ __forceinline__ PixStage<float> load_pix<float>(
 // nh (<= NH) staged hit columns starting at prow, whose in-plane xi-intervals
 // are [lo[h], hi[h]] with lo[h] <= hi[h], against the voxel's z-planes mb and
 // mb1.  Returns a + sum of w * (L e) (w^2 * le when SQ).  All NH records are
-// read before the first is used (one wait for both); the staging buffer holds
-// a spare record past its last, so prow + NH - 1 is always inside it.
+// read before the first is used; the staging buffer holds a spare record past
+// its last, so prow + NH - 1 is always inside it.
 template <typename A, bool SQ>
 __host__ __device__ __forceinline__ A add_row(const PixStage<A> *prow, int nh, const float (&lo)[NH],
                                               const float (&hi)[NH], float mb, float mb1, A a)
@@ -202,28 +202,19 @@ __host__ __device__ __forceinline__ const PixStage<A> *row_record(const PixStage
     return pg + r * CHC;
 }
 
-// Whether pred holds in every active lane of the wavefront (on a CPU build: in
-// the one lane).
-__host__ __device__ __forceinline__ bool wave_all(bool pred)
-{
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __all(pred);
-#else
-    return pred;
-#endif
-}
-
 // The voxels of one lane for one group of hit columns: voxel j (j < nzb) has
 // the planes mbz0 + j and mbz0 + j + 1 and the candidate rows va1 + 1 .. vb with
-// va1 = floor(l0 + j sl) and vb = floor(h0 + (j + 1) sh), clamped to the staged
-// rows (vlow = first staged row - 1, vmax = last) when clamp (uniform over the
-// wavefront: a scalar branch around the two clamps).  pg + va1 * CHC is the
+// va1 = floor(l0 + j sl) and vb = floor(h0 + (j + 1) sh).  The first candidate
+// row is evaluated for every voxel, without a branch: va1 is clamped to
+// [vlow, vmax + 1] (vlow = first staged row - 1, vmax = last), so row va1 + 1 is
+// a staged row or one of the two zero rows staged after them, and a row that
+// is not a candidate has weight exactly 0 (the weights are exact).  Further
+// rows, up to vb clamped to vmax, follow in a loop.  pg + va1 * CHC is the
 // record of row va1 + 1 in the group's first column.
 template <typename A, bool SQ, int CHC, int TZN>
 __host__ __device__ __forceinline__ void voxel_rows(const PixStage<A> *pg, int nh, const float (&lo)[NH],
                                                     const float (&hi)[NH], float mbz0, int nzb, float l0, float sl,
-                                                    float h0, float sh, bool clamp, int vlow, int vmax,
-                                                    A (&acc)[TZN])
+                                                    float h0, float sh, int vlow, int vmax, A (&acc)[TZN])
 {
     // The per-voxel plane values do not depend on the column group; computed
     // here they stay short-lived (hoisted out of the group loop, all TZ of them
@@ -242,23 +233,15 @@ __host__ __device__ __forceinline__ void voxel_rows(const PixStage<A> *pg, int n
             // integer lo, whose row lies 0.01 below the true bound and is rightly left out
             const float vlo = __builtin_fmaf((float)j, sl, l0), vhi = __builtin_fmaf((float)(j + 1), sh, h0);
             int va1 = (int)floorf(vlo), vb = (int)floorf(vhi);
-            if (clamp) {
-#if defined(__HIP_DEVICE_COMPILE__)
-                asm volatile("");  // keeps the branch (not two selects)
-#endif
-                va1 = va1 < vlow ? vlow : va1;
-                vb = vb > vmax ? vmax : vb;
+            va1 = va1 < vlow ? vlow : (va1 > vmax + 1 ? vmax + 1 : va1);
+            vb = vb > vmax ? vmax : vb;
+            const PixStage<A> *prow = row_record<A, CHC>(pg, va1);
+            A a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, acc[j]);
+            for (int v = va1 + 2; v <= vb; ++v) {
+                prow += CHC;
+                a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, a);
             }
-            if (va1 < vb) {
-                // the first candidate row outside the loop: most voxels have one
-                const PixStage<A> *prow = row_record<A, CHC>(pg, va1);
-                A a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, acc[j]);
-                for (int v = va1 + 2; v <= vb; ++v) {
-                    prow += CHC;
-                    a = add_row<A, SQ>(prow, nh, lo, hi, mb, mb1, a);
-                }
-                acc[j] = a;
-            }
+            acc[j] = a;
         }
         mb = mb1;
     }
@@ -266,7 +249,8 @@ __host__ __device__ __forceinline__ void voxel_rows(const PixStage<A> *pg, int n
 
 // One lane's share of one staged chunk of one view: add w_ij * (L_i e_i) to the
 // accumulators of its voxels (ix, iy, iz0 + j), j < nzb, for every staged ray
-// i = (column cu0 + c, row cv0 + r); s_pix[r * CHC + c] describes ray i.
+// i = (column cu0 + c, row cv0 + r); s_pix[r * CHC + c] describes ray i, and
+// rows nrow and nrow + 1 of s_pix hold zero records (weight 0 for any voxel).
 // SQ: accumulate w_ij^2 * le instead of w_ij * le (with le = L^2 this sums the
 // squared weights, the diagonal of A^T A).
 template <typename A, bool SQ, int CHC, int TZN>
@@ -335,14 +319,8 @@ __host__ __device__ __forceinline__ void gather_chunk(const GeoDev &g, const Vie
         const float sl = (fminf(b1, b2) - fminf(a1, a2)) * inv_nzb;
         const float sh = (fmaxf(b1, b2) - fmaxf(a1, a2)) * inv_nzb;
         const float l0 = fminf(a1, a2) + vofs_lo, h0 = fmaxf(a1, a2) + vofs_hi;
-        // Every lane's candidate rows lie in the staged chunk when its lowest
-        // (voxel 0) and highest (voxel nzb - 1) bounds do: l0 + j sl and h0 + j sh
-        // do not decrease with j (sl, sh >= 0: the plane heights in row units grow
-        // with z, and fused multiply-adds round monotonically).  A wavefront whose
-        // lanes all pass skips the clamps.
-        const bool inside = l0 >= (float)(cv0 - 1) && __builtin_fmaf((float)nzb, sh, h0) < (float)(vmax + 1);
         const PixStage<A> *pg = s_pix + ((c0 - cu0) + (1 - cv0) * CHC);  // row va1 + 1 at pg + va1 * CHC
-        voxel_rows<A, SQ, CHC, TZN>(pg, nh, lo, hi, mbz0, nzb, l0, sl, h0, sh, !wave_all(inside), cv0 - 1, vmax, acc);
+        voxel_rows<A, SQ, CHC, TZN>(pg, nh, lo, hi, mbz0, nzb, l0, sl, h0, sh, cv0 - 1, vmax, acc);
     }
 }
 
