@@ -56,6 +56,10 @@ def lib():
         L.oracle_project_rays.restype = None
         L.oracle_backproject.argtypes = geo + [dp, dp]
         L.oracle_backproject.restype = None
+        L.oracle_project32.argtypes = geo + [dp, dp]
+        L.oracle_project32.restype = None
+        L.oracle_backproject32.argtypes = geo + [dp, dp]
+        L.oracle_backproject32.restype = None
         L.oracle_backproject_voxels.argtypes = geo + [dp, i64p, ctypes.c_int64, dp]
         L.oracle_backproject_voxels.restype = None
         L.oracle_count_nnz.argtypes = geo
@@ -134,6 +138,26 @@ def project(g, x):
     return b.reshape(g.n_views, g.nv, g.nu)
 
 
+def project32(g, x):
+    """b = A x in single-precision arithmetic (weights and x rounded to float,
+    float fused multiply-adds along each ray), shape (n_views, nv, nu)."""
+    gt = _geo(g)
+    x = _vol(g, x)
+    b = np.empty(g.n_views * g.nv * g.nu, dtype=np.float64)
+    lib().oracle_project32(*_gargs(gt), _ptr(x), _ptr(b))
+    return b.reshape(g.n_views, g.nv, g.nu)
+
+
+def backproject32(g, y):
+    """r = A^T y in single-precision arithmetic (per voxel, float fused
+    multiply-adds in ray order), shape (nz, ny, nx)."""
+    gt = _geo(g)
+    y = _proj(g, y)
+    r = np.empty(g.nx * g.ny * g.nz, dtype=np.float64)
+    lib().oracle_backproject32(*_gargs(gt), _ptr(y), _ptr(r))
+    return r.reshape(g.nz, g.ny, g.nx)
+
+
 def project_rays(g, x, rays):
     """(A x)_i for the flat ray indices ``rays``."""
     gt = _geo(g)
@@ -194,7 +218,10 @@ class SolveResult:
         return f"SolveResult(iterations={self.iterations}, nb={self.nb:.6g}, stop={self.stop_reason})"
 
 
-PROJECTORS = {"siddon": 0, "tt": 1}
+# "siddon32": the Siddon pair in single-precision arithmetic (project32 /
+# backproject32), for solves in the precision structure of a single-precision
+# GPU path (with store32: vectors and projector in float, scalars in double).
+PROJECTORS = {"siddon": 0, "tt": 1, "siddon32": 2}
 
 
 def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recompute_every=0, projector="siddon",
@@ -203,7 +230,7 @@ def cgls(g, b, K, x0=None, err=0.0, literal_update=False, tikhonov=0.0, recomput
 
     tikhonov = lambda adds lambda^2 |x|^2 to the objective (CGLS on [A; lambda I]);
     recompute_every = k > 0 recomputes e = b - A x after every k-th iteration;
-    projector "siddon" or "tt" selects the operator;
+    projector "siddon", "tt" or "siddon32" selects the operator;
     store32 rounds the vectors x, r, d, e, p to single precision after every
     update (scalars and norms stay double): the single-precision storage form
     of Section 5, used to measure how far that rounding alone moves the iterates."""
@@ -250,6 +277,8 @@ def diag_normal(g):
 def cgls_jacobi(g, b, K, x0=None, err=0.0, projector="siddon"):
     """Jacobi-preconditioned CGLS (Algorithm 1 on A diag(A^T A)^(-1/2)) in FP64,
     with the Siddon or the TT operator and that operator's diagonal."""
+    if projector not in ("siddon", "tt"):
+        raise ValueError("cgls_jacobi takes the siddon or the tt operator")
     gt = _geo(g)
     b = _proj(g, b)
     x = np.zeros(g.nx * g.ny * g.nz) if x0 is None else _vol(g, x0).copy()

@@ -321,6 +321,76 @@ void oracle_backproject(const int32_t *dims, const double *par, const double *an
     }
 }
 
+/* The same pair in single-precision arithmetic, the precision of the paper's
+ * GPU projectors (Section 5): every weight and input element rounded to float,
+ * each sum formed by float fused multiply-adds (fmaf: one rounding per term),
+ * along the ray for A and per voxel in ray order for A^T.  The weights are the
+ * double-precision ones of og_trace; only their use is single precision. */
+void oracle_project32(const int32_t *dims, const double *par, const double *angles,
+                      const double *x, double *b)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t nrays = (int64_t)g.nviews * g.nv * g.nu;
+#pragma omp parallel
+    {
+        int cap = og_cap(&g);
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *w = (double *)malloc(sizeof(double) * (size_t)cap);
+        og_scratch sc = og_scratch_new(&g);
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t r = 0; r < nrays; ++r) {
+            int k = (int)(r / ((int64_t)g.nv * g.nu));
+            int iv = (int)((r / g.nu) % g.nv);
+            int iu = (int)(r % g.nu);
+            double s[3], q[3];
+            og_ray(&g, k, iv, iu, s, q);
+            int n = og_trace(&g, &sc, s, q, 0, g.nz, idx, w);
+            float acc = 0.0f;
+            for (int j = 0; j < n; ++j) acc = fmaf((float)w[j], (float)x[idx[j]], acc);
+            b[r] = (double)acc;
+        }
+        free(idx);
+        free(w);
+        og_scratch_free(&sc);
+    }
+}
+
+void oracle_backproject32(const int32_t *dims, const double *par, const double *angles,
+                          const double *y, double *r)
+{
+    og_t g = og_make(dims, par, angles);
+    int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    float *rf = (float *)calloc((size_t)nvox, sizeof(float));
+    int64_t nrays = (int64_t)g.nviews * g.nv * g.nu;
+    int nslab = 2 * omp_get_max_threads();
+    if (nslab > g.nz) nslab = g.nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int sl = 0; sl < nslab; ++sl) {
+        int zlo = (int)((int64_t)g.nz * sl / nslab);
+        int zhi = (int)((int64_t)g.nz * (sl + 1) / nslab);
+        int cap = og_cap(&g);
+        int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+        double *w = (double *)malloc(sizeof(double) * (size_t)cap);
+        og_scratch sc = og_scratch_new(&g);
+        for (int64_t ri = 0; ri < nrays; ++ri) {
+            if (y[ri] == 0.0) continue;
+            int k = (int)(ri / ((int64_t)g.nv * g.nu));
+            int iv = (int)((ri / g.nu) % g.nv);
+            int iu = (int)(ri % g.nu);
+            double s[3], q[3];
+            og_ray(&g, k, iv, iu, s, q);
+            int n = og_trace(&g, &sc, s, q, zlo, zhi, idx, w);
+            const float yf = (float)y[ri];
+            for (int j = 0; j < n; ++j) rf[idx[j]] = fmaf((float)w[j], yf, rf[idx[j]]);
+        }
+        free(idx);
+        free(w);
+        og_scratch_free(&sc);
+    }
+    for (int64_t i = 0; i < nvox; ++i) r[i] = (double)rf[i];
+    free(rf);
+}
+
 /* diag(A^T A)_j = sum_i w_ij^2 (the squared column norms of A; the diagonal of
  * the normal equations that Jacobi preconditioning uses, Section 5).  Same
  * slab-parallel scatter as the backprojection, with squared weights. */
@@ -535,11 +605,14 @@ static int og_progress_flag(void)
 }
 #define og_progress og_progress_flag()
 
-/* The operator of a solve: the Siddon pair (projector 0) or the TT pair (1). */
+/* The operator of a solve: the Siddon pair (projector 0), the TT pair (1), or
+ * the Siddon pair in single-precision arithmetic (projector 2, see
+ * oracle_project32). */
 static void og_A(int projector, const int32_t *dims, const double *par, const double *angles, const double *x,
                  double *b)
 {
     if (projector == 1) oracle_tt_project(dims, par, angles, x, b);
+    else if (projector == 2) oracle_project32(dims, par, angles, x, b);
     else oracle_project(dims, par, angles, x, b);
 }
 
@@ -547,6 +620,7 @@ static void og_AT(int projector, const int32_t *dims, const double *par, const d
                   double *r)
 {
     if (projector == 1) oracle_tt_backproject(dims, par, angles, y, r);
+    else if (projector == 2) oracle_backproject32(dims, par, angles, y, r);
     else oracle_backproject(dims, par, angles, y, r);
 }
 

@@ -26,7 +26,18 @@ single-precision input the library is given), and the file holds:
                   precision (the oracle's store32 option), i.e. how far
                   single-precision storage alone moves the K-th iterate
   history32       NB_k / NB0 of that single-precision-storage solve
+  spread_f32_idx  |x_K - x_K(f32)| / |x_K| on the sampled voxels (spread_f32 over
+                  the volume when the file is written in one run), history_f32,
+                  err_truth_f32: the same solver in the precision
+                  structure of a single-precision GPU path -- vectors stored in
+                  float and the projector pair computed in float (the oracle's
+                  "siddon32" operator with store32), scalars in double
   seconds         wall time of the FP64 solve, threads, CPU model
+
+    python tests/golden/make_solver_goldens.py --add-f32 [case ...]
+
+adds the spread_f32 fields to existing files (the FP64 results are kept; the
+regenerated data must hash to the stored value).
 A Markdown summary of the oracle timings goes to profiles/oracle_solver_timings.md.
 """
 from __future__ import annotations
@@ -113,27 +124,46 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _solve(cache: dict, cfg: str, solver: str, K: int, store32: bool):
-    """One oracle solve, computed once per (configuration, solver, K, storage)
-    and shared by the cases that need it; returns (result, seconds)."""
-    key = (cfg, solver, K, store32)
+def _solve(cache: dict, cfg: str, solver: str, K: int, store32: bool, projector: str = "siddon"):
+    """One oracle solve, computed once per (configuration, solver, K, storage,
+    operator) and shared by the cases that need it; returns (result, seconds)."""
+    key = (cfg, solver, K, store32, projector)
     if key not in cache:
         g, _, b32 = cache[cfg]
         t = time.perf_counter()
-        res = getattr(oracle, solver)(g, b32.astype(np.float64), K, store32=store32)
+        res = getattr(oracle, solver)(g, b32.astype(np.float64), K, store32=store32, projector=projector)
         secs = time.perf_counter() - t
-        print(f"[golden] {cfg}: {'store32 ' if store32 else 'FP64 '}{solver} K={K} in {secs:.1f} s", flush=True)
+        tag = "f32 " if projector == "siddon32" else ("store32 " if store32 else "FP64 ")
+        print(f"[golden] {cfg}: {tag}{solver} K={K} in {secs:.1f} s", flush=True)
         cache[key] = (res, secs)
     return cache[key]
 
 
-def run_case(name: str, cache: dict) -> dict:
-    cfg, solver, K = CASES[name]
+def _data_cached(cfg: str, cache: dict):
     if cfg not in cache:
         t = time.perf_counter()
         cache[cfg] = problem_data(cfg)
         print(f"[golden] {cfg}: data in {time.perf_counter() - t:.1f} s", flush=True)
-    g, x_true, b32 = cache[cfg]
+    return cache[cfg]
+
+
+def f32_fields(name: str, cache: dict, x_idx: np.ndarray, idx: np.ndarray, x=None) -> dict:
+    """The single-precision-structure yardstick of a case: its spread from the
+    FP64 iterate on the sampled voxels (x_idx = x_K[idx]) and, when the whole
+    FP64 iterate x is at hand, over the volume."""
+    cfg, solver, K = CASES[name]
+    _, x_true, _ = _data_cached(cfg, cache)
+    rf, _ = _solve(cache, cfg, solver, K, True, "siddon32")
+    out = {"spread_f32_idx": rel(rf.x.ravel()[idx], x_idx), "history_f32": rf.history,
+           "err_truth_f32": rel(rf.x, x_true)}
+    if x is not None:
+        out["spread_f32"] = rel(rf.x, x)
+    return out
+
+
+def run_case(name: str, cache: dict) -> dict:
+    cfg, solver, K = CASES[name]
+    g, x_true, b32 = _data_cached(cfg, cache)
     other = "lsqr" if solver == "cgls" else "cgls"
     res, secs = _solve(cache, cfg, solver, K, False)
     alt, _ = _solve(cache, cfg, other, K, False)
@@ -151,7 +181,22 @@ def run_case(name: str, cache: dict) -> dict:
         "history32": r32.history,
         "seconds": secs, "threads": oracle.num_threads(), "cpu": cpu_model(),
     }
+    out.update(f32_fields(name, cache, x[idx], idx, x))
     return out
+
+
+def add_f32(name: str, cache: dict) -> dict:
+    """Load a stored case, check its data, add the spread_f32 fields."""
+    path = os.path.join(HERE, f"{name}.npz")
+    with np.load(path, allow_pickle=False) as z:
+        rec = {k: z[k][()] if z[k].ndim == 0 else z[k].copy() for k in z.files}
+    cfg, _, _ = CASES[name]
+    g, _, b32 = _data_cached(cfg, cache)
+    if b_hash(b32) != str(rec["b_sha256"]):
+        raise SystemExit(f"{name}: regenerated data differ from the stored input")
+    # the FP64 iterate is stored on the sampled voxels only
+    rec.update(f32_fields(name, cache, np.asarray(rec["x_idx"]), np.asarray(rec["idx"])))
+    return rec
 
 
 def save(name: str, rec: dict) -> str:
@@ -178,6 +223,9 @@ def write_timings(recs: dict) -> None:
 
 
 def main(argv):
+    add = bool(argv) and argv[0] == "--add-f32"
+    if add:
+        argv = argv[1:]
     names = argv or list(CASES)
     for n in names:
         if n not in CASES:
@@ -185,10 +233,12 @@ def main(argv):
     oracle.build(force=False)
     cache: dict = {}
     for name in names:
-        rec = run_case(name, cache)
+        rec = add_f32(name, cache) if add else run_case(name, cache)
         path = save(name, rec)
-        summary = {k: (float(v) if isinstance(v, (float, np.floating)) else v) for k, v in rec.items()
-                   if k in ("K", "err_truth", "err_truth32", "spread_alt", "spread32", "spread32_idx", "seconds")}
+        summary = {k: (float(v) if isinstance(v, (float, np.floating)) else int(v) if isinstance(v, np.integer) else v)
+                   for k, v in rec.items()
+                   if k in ("K", "err_truth", "err_truth32", "err_truth_f32", "spread_alt", "spread32", "spread32_idx",
+                            "spread_f32", "spread_f32_idx", "seconds")}
         print(f"[golden] wrote {os.path.relpath(path, ROOT)} {json.dumps(summary)}", flush=True)
     recs = {}
     for name in CASES:

@@ -609,3 +609,59 @@ def test_results_do_not_depend_on_thread_count():
     finally:
         oracle.set_num_threads(n)
     assert np.array_equal(a1, a2) and np.array_equal(r1, r2) and np.array_equal(c1, c2)
+
+
+U32 = 2.0 ** -24  # unit roundoff of single precision
+
+
+def _gamma(k):
+    """gamma_k = k u / (1 - k u): the bound on the relative error of k
+    successive single-precision roundings (Higham, Accuracy and Stability of
+    Numerical Algorithms, Lemma 3.1)."""
+    return k * U32 / (1.0 - k * U32)
+
+
+@pytest.mark.parametrize("variant", ["base", "odd", "offcenter"])
+def test_single_precision_projector_within_the_summation_bound(variant):
+    """The single-precision form of the pair (Section 5: the GPU projectors
+    compute in float) rounds every weight and input element once and every
+    partial sum once per term, so per ray |A32 x - A x| <= gamma_(n+2) (|A| |x|)
+    with n the ray's nonzeros, and per voxel likewise over its column (the
+    standard bound for recursive fused multiply-add summation of rounded
+    products).  A dropped, doubled or misplaced term breaks the bound by a
+    factor ~1e6; a no-op (double arithmetic) is caught by the rounding checks."""
+    g = ki.t16(variant)
+    A = oracle.assemble(g)
+    absA = abs(A)
+    x = ki.random_volume(g, 21) - 0.5
+    y = ki.random_projections(g, 22) - 0.5
+    b64, b32 = oracle.project(g, x).ravel(), oracle.project32(g, x).ravel()
+    r64, r32 = oracle.backproject(g, y).ravel(), oracle.backproject32(g, y).ravel()
+    n_row = np.diff(A.indptr)
+    n_col = np.diff(A.tocsc().indptr)
+    bound_b = np.array([_gamma(k + 2) for k in n_row]) * (absA @ np.abs(x.ravel())) * (1 + 1e-9) + 1e-300
+    bound_r = np.array([_gamma(k + 2) for k in n_col]) * (absA.T @ np.abs(y.ravel())) * (1 + 1e-9) + 1e-300
+    assert np.all(np.abs(b32 - b64) <= bound_b)
+    assert np.all(np.abs(r32 - r64) <= bound_r)
+    # single precision in fact: every result is a float, and the results differ
+    assert np.array_equal(b32, b32.astype(np.float32).astype(np.float64))
+    assert np.array_equal(r32, r32.astype(np.float32).astype(np.float64))
+    assert np.any(b32 != b64) and np.any(r32 != r64)
+
+
+def test_single_precision_solve_stays_near_the_double_solve(small_problem):
+    """CGLS and LSQR with the single-precision pair and single-precision storage
+    (the precision structure of a float GPU path with double scalars): iterates
+    are floats, within single-precision rounding of the FP64 solve at small K,
+    and not equal to it; the preconditioned solver refuses the form."""
+    g, A, b = small_problem
+    b32 = b.astype(np.float32).astype(np.float64)
+    for solver in ("cgls", "lsqr"):
+        full = getattr(oracle, solver)(g, b32, 4)
+        res = getattr(oracle, solver)(g, b32, 4, projector="siddon32", store32=True)
+        x = res.x.ravel()
+        assert np.array_equal(x, x.astype(np.float32).astype(np.float64))
+        assert 0.0 < rel(x, full.x) < 1e-5
+        np.testing.assert_allclose(res.history, full.history, rtol=1e-5)
+    with pytest.raises(ValueError):
+        oracle.cgls_jacobi(g, b32, 2, projector="siddon32")
