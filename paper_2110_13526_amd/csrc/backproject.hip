@@ -64,7 +64,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
 
     // the brick's column in the shadow table, and its lowest and highest plane
     // (heights above the source plane, mm)
-    const int sbi = by * g.sbx + bx;
+    const int sbi = __builtin_amdgcn_readfirstlane(by * g.sbx + bx);  // uniform: the table row stays scalar
     const size_t sbxy = (size_t)g.sbx * g.sby;
     const float wz0 = g.z0 + (float)iz0 * g.vz, wz1 = g.z0 + (float)(iz0 + nzb) * g.vz;
 
@@ -148,7 +148,12 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 }
                 __syncthreads();
                 // 3. gather
-                if (valid) gather_chunk<A, SQ, CHC>(g, vp, ix, iy, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
+                // the lane's column indices laundered per chunk: the few values derived
+                // from them are recomputed here instead of being kept live (and spilled)
+                // through the view loop
+                int ixv = ix, iyv = iy;
+                asm volatile("" : "+v"(ixv), "+v"(iyv));
+                if (valid) gather_chunk<A, SQ, CHC>(g, vp, ixv, iyv, iz0, nzb, s_pix, s_col, cu0, ncol, cv0, nrow, acc);
                 __syncthreads();
             }
         }
