@@ -295,6 +295,22 @@ kct_status kct_batch_cgls_solve(kct_batch b, const float *const *bs, float *cons
  * yet), UNSUPPORTED (no device wall clock), HIP. */
 kct_status kct_batch_latencies(kct_batch b, double *seconds);
 
+/* Launch timing of the solvers' projector steps, for measurement (not part of
+ * the method).  kct_timing_enable(1) clears the record and from then on every
+ * forward (p = A d in CGLS, the u update in LSQR) and backward (r = A^T e, the
+ * v update) launch of a kct_cgls_solve / kct_lsqr_solve iteration is
+ * bracketed by a HIP event pair on the solve's stream; kct_timing_enable(0)
+ * stops recording (and clears).  Process-wide, not thread-safe: time one solve
+ * at a time.  Events are created on first use and reused.  Errors: HIP (from
+ * the solve that records). */
+kct_status kct_timing_enable(int32_t on);
+
+/* The launches recorded since kct_timing_enable(1) of one kind (0 forward,
+ * 1 backward): their number and the average, smallest and largest duration in
+ * milliseconds (host outputs; 0 when none).  Waits for the recorded events.
+ * Errors: INVALID_ARG (other kind, NULL output), HIP. */
+kct_status kct_timing_get(int32_t kind, int32_t *count, double *avg_ms, double *min_ms, double *max_ms);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *kct_last_error(void);
 

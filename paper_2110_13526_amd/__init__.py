@@ -306,6 +306,22 @@ def lsqr(g: Geometry, b, K: int, x0=None, err: float = 0.0, history: bool = Fals
     return _solve("lsqr", g, b, K, x0, err, history, workspace, out, tikhonov)
 
 
+def timing_enable(on: bool = True):
+    """Start (clearing the record) or stop recording the duration of every
+    projector launch of the solvers' iterations (kct_timing_enable)."""
+    _lib.check(_lib.load().kct_timing_enable(1 if on else 0))
+
+
+def timing_get(kind: str):
+    """(count, average ms, min ms, max ms) of the recorded "forward" or
+    "backward" launches (kct_timing_get)."""
+    n = ctypes.c_int32(0)
+    avg, lo, hi = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+    _lib.check(_lib.load().kct_timing_get({"forward": 0, "backward": 1}[kind], ctypes.byref(n), ctypes.byref(avg),
+                                          ctypes.byref(lo), ctypes.byref(hi)))
+    return n.value, avg.value, lo.value, hi.value
+
+
 class Batch:
     """Batched CGLS over independent reconstructions with their own geometries
     (kct_batch_* in include/kct.h): every step of Algorithm 1 is one launch for

@@ -23,7 +23,7 @@ EXPORTS = (
     "kct_project", "kct_backproject", "kct_solver_workspace_size", "kct_cgls_solve", "kct_lsqr_solve",
     "kct_diag_normal", "kct_batch_create", "kct_batch_destroy", "kct_batch_workspace_size", "kct_batch_tune",
     "kct_batch_cgls_solve", "kct_geometry_set_projector", "kct_last_error", "kct_project_noalloc",
-    "kct_batch_latencies",
+    "kct_batch_latencies", "kct_timing_enable", "kct_timing_get",
 )
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -89,6 +89,11 @@ def load():
     L.kct_project_noalloc.restype = st
     L.kct_batch_latencies.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.kct_batch_latencies.restype = st
+    L.kct_timing_enable.argtypes = [ctypes.c_int32]
+    L.kct_timing_enable.restype = st
+    dptr = ctypes.POINTER(ctypes.c_double)
+    L.kct_timing_get.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dptr, dptr, dptr]
+    L.kct_timing_get.restype = st
     L.kct_backproject.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.kct_backproject.restype = st
     L.kct_solver_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kct_internal.h"
 
@@ -17,6 +18,42 @@ void set_error(const std::string &msg) { g_last_error = msg; }
 kct_status geometry_build(const kct_volume_desc &vol, const kct_cone_desc &cone, Geometry *g);
 
 namespace {
+
+// Launch timing of the solvers' projector steps (kct_timing_enable): one HIP
+// event pair around every forward and backward launch of a CGLS / LSQR
+// iteration, recorded on the solve's stream.  Process-wide; events are
+// created on first use and reused.
+struct LaunchTimer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<std::pair<size_t, size_t>> pairs[2];  // per kind (0 forward, 1 backward): start, stop
+    hipError_t next(size_t &i)
+    {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            pool.push_back(e);
+        }
+        i = used++;
+        return hipSuccess;
+    }
+    hipError_t begin(hipStream_t st, size_t &i0)
+    {
+        hipError_t r = next(i0);
+        return r != hipSuccess ? r : hipEventRecord(pool[i0], st);
+    }
+    hipError_t end(int kind, hipStream_t st, size_t i0)
+    {
+        size_t i1;
+        hipError_t r = next(i1);
+        if (r == hipSuccess) r = hipEventRecord(pool[i1], st);
+        if (r == hipSuccess) pairs[kind].push_back({i0, i1});
+        return r;
+    }
+};
+LaunchTimer g_timer;
 
 size_t elem_size(kct_dtype t)
 {
@@ -129,6 +166,16 @@ template <> kct_dtype dtype_of<_Float16>() { return KCT_F16; }
             set_error(std::string(fn) + ": " #expr " failed: " + hipGetErrorString(e_));         \
             return KCT_ERR_HIP;                                                                  \
         }                                                                                        \
+    } while (0)
+
+// A projector launch of a solver iteration, timed when kct_timing_enable is on
+// (kind 0 forward, 1 backward).
+#define KCT_TIMED(kind, st, expr)                                                                \
+    do {                                                                                         \
+        size_t i0_ = 0;                                                                          \
+        if (g_timer.on) KCT_TRY(g_timer.begin(st, i0_));                                         \
+        KCT_TRY(expr);                                                                           \
+        if (g_timer.on) KCT_TRY(g_timer.end(kind, st, i0_));                                     \
     } while (0)
 
 struct StorageScales {
@@ -302,22 +349,22 @@ kct_status cgls_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         return KCT_OK;
     };
     // r = A^T e; d = r; NR2_old = |r|^2
-    KCT_TRY(launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux));
+    KCT_TIMED(1, st, (launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux)));
     KCT_TRY(launch_finalize(sc, part, nbk, F_NR2_INIT, st));
     KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 1, st, dpart));
     // p = A d; NP2 = |p|^2 (+ lambda^2 |d|^2); alpha = NR2_old / NP2
-    KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
+    KCT_TIMED(0, st, (launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
     KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st, dpart, nd));
     kct_status s = step_end(1);
     if (s != KCT_OK) return s;
     for (int it = 1; it < K; ++it) {
         // r = A^T e; NR2_now = |r|^2; beta = NR2_now / NR2_old; NR2_old = NR2_now
-        KCT_TRY(launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux));
+        KCT_TIMED(1, st, (launch_backward<T>(G, e, r, nullptr, repi, sc, part, done, st, raux)));
         KCT_TRY(launch_finalize(sc, part, nbk, F_BETA, st));
         // d = r + beta d
         KCT_TRY(launch_cgls_d<T>(G, r, d, dz, sc, 0, st, dpart));
         // p = A d; NP2; alpha
-        KCT_TRY((launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
+        KCT_TIMED(0, st, (launch_forward<T, T>(G, d, dz, p, nullptr, FWD_NORM, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_ALPHA, st, dpart, nd));
         if ((s = step_end(it + 1)) != KCT_OK) return s;
     }
@@ -364,15 +411,15 @@ kct_status lsqr_t(const Geometry *g, const void *bv, void *xv, const kct_solve_o
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA0, st));
     }
     // alpha v = A^T u; w = v
-    KCT_TRY(launch_backward<T>(G, u, v, vz, BWD_LSQR0, sc, part, done, st));
+    KCT_TIMED(1, st, (launch_backward<T>(G, u, v, vz, BWD_LSQR0, sc, part, done, st)));
     KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA0, st));
     KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 1, n, st));
     for (int it = 0; it < K; ++it) {
         // beta u = A v - alpha u
-        KCT_TRY((launch_forward<T, T>(G, v, vz, u, nullptr, FWD_LSQR, sc, part, done, st)));
+        KCT_TIMED(0, st, (launch_forward<T, T>(G, v, vz, u, nullptr, FWD_LSQR, sc, part, done, st)));
         KCT_TRY(launch_finalize(sc, part, nf, F_L_BETA, st));
         // alpha v = A^T u - beta v (skipped on the last iteration), Givens rotation
-        KCT_TRY(launch_backward<T>(G, u, v, vz, BWD_LSQR, sc, part, &sc->skip_bwd, st));
+        KCT_TIMED(1, st, (launch_backward<T>(G, u, v, vz, BWD_LSQR, sc, part, &sc->skip_bwd, st)));
         KCT_TRY(launch_finalize(sc, part, nbk, F_L_ALPHA, st));
         // x += (phi / rho) w; w = v - (theta / rho) w
         KCT_TRY(launch_lsqr_xw<T>(x, w, v, sc, 0, n, st));
@@ -605,6 +652,40 @@ kct_status kct_diag_normal(kct_geometry h, float *out, hipStream_t stream)
     }
     const Geometry *g = reinterpret_cast<const Geometry *>(h);
     KCT_TRY(launch_backward<float>(g->dev, nullptr, out, nullptr, BWD_DIAG, nullptr, nullptr, nullptr, stream));
+    return KCT_OK;
+}
+
+kct_status kct_timing_enable(int32_t on)
+{
+    g_timer.on = on != 0;
+    g_timer.used = 0;
+    g_timer.pairs[0].clear();
+    g_timer.pairs[1].clear();
+    return KCT_OK;
+}
+
+kct_status kct_timing_get(int32_t kind, int32_t *count, double *avg_ms, double *min_ms, double *max_ms)
+{
+    const char *fn = "kct_timing_get";
+    if ((kind != 0 && kind != 1) || !count || !avg_ms || !min_ms || !max_ms) {
+        set_error("kct_timing_get: kind must be 0 or 1 and the outputs non-NULL");
+        return KCT_ERR_INVALID_ARG;
+    }
+    double sum = 0.0, lo = 0.0, hi = 0.0;
+    int32_t n = 0;
+    for (const auto &pr : g_timer.pairs[kind]) {
+        KCT_TRY(hipEventSynchronize(g_timer.pool[pr.second]));
+        float ms = 0.0f;
+        KCT_TRY(hipEventElapsedTime(&ms, g_timer.pool[pr.first], g_timer.pool[pr.second]));
+        lo = n == 0 ? ms : (ms < lo ? ms : lo);
+        hi = n == 0 ? ms : (ms > hi ? ms : hi);
+        sum += ms;
+        ++n;
+    }
+    *count = n;
+    *avg_ms = n ? sum / n : 0.0;
+    *min_ms = lo;
+    *max_ms = hi;
     return KCT_OK;
 }
 
