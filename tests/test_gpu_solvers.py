@@ -136,3 +136,32 @@ def test_cgls_c2_properties():
     assert rel(got, alpha * ref_r0) < TOL
     del x, xl, x1, r0, ar0, b
     torch.cuda.empty_cache()
+
+
+def test_launch_timing_counts_every_iteration_launch():
+    """The launch timing brackets every projector launch of a solve's
+    iterations: K forward and K backward launches for CGLS (the backward that
+    starts the first iteration included), K and K + 1 for LSQR (its
+    bidiagonalisation starts with A^T b); durations are positive and ordered;
+    disabling clears the record."""
+    import paper_2110_13526_amd as kct
+    g = ki.t16("base")
+    G = geometry(g)
+    b = to_dev(ki.random_projections(g, 7).astype(np.float32))
+    K = 5
+    try:
+        kct.timing_enable(True)
+        kct.cgls(G, b, K)
+        for kind, want in (("forward", K), ("backward", K)):
+            n, avg, lo, hi = kct.timing_get(kind)
+            assert n == want, (kind, n)
+            assert 0.0 < lo <= avg <= hi
+        kct.timing_enable(True)  # clears
+        kct.lsqr(G, b, K)
+        assert kct.timing_get("forward")[0] == K
+        assert kct.timing_get("backward")[0] == K + 1
+    finally:
+        kct.timing_enable(False)
+    assert kct.timing_get("forward")[0] == 0 and kct.timing_get("backward")[0] == 0
+    with pytest.raises(Exception):
+        kct.timing_get("sideways")
