@@ -23,6 +23,16 @@ __host__ __device__ __forceinline__ int uniform_int(int v)
 #endif
 }
 
+// x unchanged, as a value the compiler has to hold in a register where this
+// stands: a computation on it cannot move above that point (on the host: x).
+__host__ __device__ __forceinline__ unsigned settle(unsigned x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(x));
+#endif
+    return x;
+}
+
 // Element m of a z-column as an accumulator value, 0 for m outside [0, nz)
 // (cells outside the volume).  ZCol<T, 1> is a column of the z-fastest copy:
 // on the GPU a buffer resource over the column's nz elements (built in scalar
@@ -35,11 +45,17 @@ template <typename T, int SZ> struct ZCol {
     const T *col;
     int nz, sz;
     __host__ __device__ __forceinline__ ZCol(const T *c, int n, int s) : col(c), nz(n), sz(s) {}
-    __host__ __device__ __forceinline__ acc_t<T> at(int m) const
+    __host__ __device__ __forceinline__ T raw(int m) const
     {
         const bool in = (unsigned)m < (unsigned)nz;
-        const acc_t<T> v = to_acc(col[in ? (unsigned)m * (unsigned)(SZ == 1 ? 1 : sz) : 0u]);
-        return in ? v : acc_t<T>(0);
+        const T v = col[in ? (unsigned)m * (unsigned)(SZ == 1 ? 1 : sz) : 0u];
+        return in ? v : T{};
+    }
+    __host__ __device__ __forceinline__ acc_t<T> at(int m) const { return to_acc(raw(m)); }
+    // the bits of a 2-byte element, zero-extended
+    __host__ __device__ __forceinline__ unsigned bits16(int m) const
+    {
+        return (unsigned)__builtin_bit_cast(unsigned short, raw(m));
     }
 };
 
@@ -50,17 +66,22 @@ template <typename T> struct ZCol<T, 1> {
         : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(c), (short)0, nz * (int)sizeof(T), 0x00020000))
     {
     }
-    __device__ __forceinline__ acc_t<T> at(int m) const
+    __device__ __forceinline__ T raw(int m) const
     {
         const int boff = m * (int)sizeof(T);  // m outside [0, nz): beyond the resource, read as 0
         if constexpr (sizeof(T) == 4) {
-            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, boff, 0, 0)));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rsrc, boff, 0, 0));
         } else if constexpr (sizeof(T) == 2) {
-            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, boff, 0, 0)));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rsrc, boff, 0, 0));
         } else {
             static_assert(sizeof(T) == 8, "4-, 2- or 8-byte storage");
-            return to_acc(__builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, boff, 0, 0)));
+            return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rsrc, boff, 0, 0));
         }
+    }
+    __device__ __forceinline__ acc_t<T> at(int m) const { return to_acc(raw(m)); }
+    __device__ __forceinline__ unsigned bits16(int m) const
+    {
+        return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(rsrc, m * 2, 0, 0);
     }
 };
 #endif
@@ -272,18 +293,26 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
         first_cells(t0, t1, w, m, w2, m2);
         const T *col = vol + uniform_int(base);
         const ZCol<T, SZ> zc(col, nz, sz);
-        // the current cells' loads go out together.  With 4- and 8-byte storage
-        // a crossed cell is read only in the lanes whose ray enters it: the
-        // loads' cost grows with the lanes that take part, and most pieces cross
-        // no z-plane (measured at 512^3 x 720: 78.3 -> 69.1 ms).  With 2-byte
-        // storage every lane reads it (the masked form measured 75.8 -> 80.2 ms).
+        // the current cells' loads go out together; a crossed cell is read only
+        // in the lanes whose ray enters it (the loads' cost grows with the lanes
+        // that take part, and most pieces cross no z-plane).  2-byte values are
+        // widened after the lanes rejoin, so that no lane waits for its load
+        // inside the masked region
         acc_t<T> v[R], v2[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) v[r] = zc.at(m[r]);
+        if constexpr (sizeof(T) >= 4) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if constexpr (sizeof(T) >= 4) v2[r] = m2[r] != m[r] ? zc.at(m2[r]) : acc_t<T>(0);
-            else v2[r] = zc.at(m2[r]);
+            for (int r = 0; r < R; ++r) v2[r] = m2[r] != m[r] ? zc.at(m2[r]) : acc_t<T>(0);
+        } else {
+            unsigned x2[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                x2[r] = 0u;
+                if (m2[r] != m[r]) x2[r] = zc.bits16(m2[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) v2[r] = to_acc(__builtin_bit_cast(T, (unsigned short)settle(x2[r])));
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
