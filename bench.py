@@ -101,6 +101,8 @@ def main():
                     help="profiling pass: one forward, one backward, one CGLS iteration (the solver's "
                          "instantiations) and one 1 GiB device copy (the calibration of the HBM byte "
                          "counters), nothing timed")
+    ap.add_argument("--tt-pair", action="store_true",
+                    help="with --kernels-only: also one forward and one backward of the TT footprint pair")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,11 +143,21 @@ def main():
         xk = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)
         kct.cgls(G, b, 1, workspace=wsk, out=xk)
         del wsk, xk
+        if args.tt_pair:
+            G.set_projector("tt")
+            pbuf = torch.empty(g.proj_shape, dtype=tdt, device=dev)
+            vbuf = torch.empty(g.vol_shape, dtype=tdt, device=dev)
+            pws = torch.empty(G.project_workspace_bytes(tdt), dtype=torch.uint8, device=dev)
+            kct.project(G, xin, out=pbuf, workspace=pws)
+            kct.backproject(G, b, out=vbuf)
+            G.set_projector("siddon")
+            del pbuf, vbuf, pws
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB read, 1 GiB written
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        log("[bench] kernels-only pass done: forward, backward, one CGLS iteration, 1 GiB copy")
+        log("[bench] kernels-only pass done: forward, backward, one CGLS iteration, "
+            + ("the TT pair, " if args.tt_pair else "") + "1 GiB copy")
         return
     ws = torch.empty(G.solver_workspace_bytes(tdt, "cgls"), dtype=torch.uint8, device=dev)
     out = torch.empty(g.vol_shape, dtype=torch.float32, device=dev)  # the iterate is always FP32
@@ -246,8 +258,15 @@ def main():
         t_fwd_tt = timed(lambda: kct.project(G, xin, out=pbuf, workspace=pws), 2)
         t_bwd_tt = timed(lambda: kct.backproject(G, b, out=vbuf), 2)
         G.set_projector("siddon")
+        # each operand read once and the result written once: the least HBM
+        # traffic of a launch; the TT pair is bound by its arithmetic (VALU
+        # issue), far from this
+        io_bytes = (g.n_vox + g.n_rays) * s_bytes
         tt = {"forward_ms": round(t_fwd_tt * 1e3, 3), "backward_ms": round(t_bwd_tt * 1e3, 3),
-              "pair_per_s": round(1.0 / (t_fwd_tt + t_bwd_tt), 4)}
+              "pair_per_s": round(1.0 / (t_fwd_tt + t_bwd_tt), 4), "bound": "alu",
+              "io_bytes_per_launch": io_bytes,
+              "io_frac_of_hbm": [round(io_bytes / t_fwd_tt / 1e9 / HBM_PEAK_GBS, 5),
+                                 round(io_bytes / t_bwd_tt / 1e9 / HBM_PEAK_GBS, 5)]}
         log(f"[bench] TT pair: forward {t_fwd_tt * 1e3:.2f} ms, backward {t_bwd_tt * 1e3:.2f} ms per launch")
 
     cpu = None
