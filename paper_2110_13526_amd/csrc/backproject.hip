@@ -121,8 +121,8 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                         const RowParam rp = *byte_at<RowParam>(g.rows, (unsigned)(cv0 + r) * (unsigned)sizeof(RowParam));
                         const bool par = rp.inv_qz == 0.0f;
                         PixStage<A> ps;
-                        ps.zc = zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f);
                         ps.czr = par ? PAR_INV : zeta_inv_slope(rp.inv_qz, cp.kz);
+                        ps.nzc = zeta_offset(zeta_centre(rp.qz, cp.tcv, g.zc) + (par ? pzadd : 0.0f), ps.czr);
                         const A L = (A)ray_length_per_xi(cp.lxy2, rp.qz, cp.gp);
                         ps.le = SQ ? L * L : L * ev;
                         s_pix[r * CHC + c] = ps;
@@ -141,7 +141,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                     const int zr = threadIdx.x < ncol ? nrow : nrow + 1;
                     const int zcol = threadIdx.x < ncol ? (int)threadIdx.x : (int)threadIdx.x - ncol;
                     PixStage<A> z{};
-                    z.zc = 0.0f;
+                    z.nzc = 0.0f;
                     z.czr = 0.0f;
                     z.le = (A)0;
                     s_pix[zr * CHC + zcol] = z;

@@ -50,16 +50,17 @@ struct ColStage {  // per staged detector column: in-plane ray parameters
 // parallel case.
 constexpr float PAR_INV = 1.0e30f;
 
-// Per staged pixel.  zc and czr are zeta at xi = 0 and d xi / d zeta of the
-// pixel's ray (zeta_centre and zeta_inv_slope of its row and column); rows
-// whose rays are parallel to the z-planes (qz == 0) staged as above.
+// Per staged pixel.  czr is d xi / d zeta of the pixel's ray and nzc its
+// zeta_offset (from zeta at xi = 0: zeta_centre and zeta_inv_slope of its row
+// and column); rows whose rays are parallel to the z-planes (qz == 0) staged
+// as above.
 template <typename A> struct PixStage {
-    float zc, czr;
+    float nzc, czr;
     A le;          // L * e, in the accumulator precision
     float pad;
 };
 template <> struct PixStage<double> {  // the same 16 bytes with a double L * e
-    float zc, czr;
+    float nzc, czr;
     double le;
 };
 
@@ -147,7 +148,7 @@ template <> __host__ __device__ __forceinline__ PixStage<float> load_pix<float>(
 {
     const float4 v = *reinterpret_cast<const float4 *>(p);
     PixStage<float> r;
-    r.zc = v.x;
+    r.nzc = v.x;
     r.czr = v.y;
     r.le = v.z;
     r.pad = v.w;
@@ -170,7 +171,7 @@ __host__ __device__ __forceinline__ A add_row(const PixStage<A> *prow, int nh, c
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
         if (h == 0 || h < nh) {
-            const float b0 = cross_at(mb, p[h].zc, p[h].czr), b1 = cross_at(mb1, p[h].zc, p[h].czr);
+            const float b0 = zeta_cross(mb, p[h].nzc, p[h].czr), b1 = zeta_cross(mb1, p[h].nzc, p[h].czr);
             // With lo <= hi, med3(hi, b0, b1) - med3(lo, b0, b1) is the overlap
             // min(hi, max(b0, b1)) - max(lo, min(b0, b1)) wherever that is positive
             // (both medians then pick those operands) and exactly 0 elsewhere (both

@@ -102,7 +102,7 @@ template <typename T> struct ZCol<T, 1> {
 struct ZWalk {
     int mz, stz;
     float hbf, fstz;
-    float lz, hzv, zeta_c, czr;
+    float lz, hzv, nzc, czr;  // nzc = zeta_offset(zeta_c, czr)
 };
 
 // Move the walk into the next z-cell along the ray.
@@ -111,7 +111,7 @@ __host__ __device__ __forceinline__ void zwalk_step(ZWalk &s)
     s.lz = s.hzv;
     s.mz += s.stz;
     s.hbf += s.fstz;
-    s.hzv = cross_at(s.hbf, s.zeta_c, s.czr);
+    s.hzv = zeta_cross(s.hbf, s.nzc, s.czr);
 }
 
 // Start the z-walk of a ray at the in-plane entry t_start: in the cell of
@@ -122,7 +122,7 @@ __host__ __device__ __forceinline__ void zwalk_step(ZWalk &s)
 __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, float czr, int nz, float hz,
                                                     float t_start, float t_end)
 {
-    s.zeta_c = zeta_c;
+    s.nzc = zeta_offset(zeta_c, czr);
     s.czr = czr;
     s.hbf = 0.0f;
     s.fstz = 0.0f;
@@ -134,7 +134,7 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
         if (s.mz < 0 || s.mz >= nz) { s.mz = -1; s.lz = INFINITY; }
         return;
     }
-    const float b0 = cross_at(-hz, zeta_c, czr), b1 = cross_at((float)nz - hz, zeta_c, czr);
+    const float b0 = zeta_cross(-hz, s.nzc, czr), b1 = zeta_cross((float)nz - hz, s.nzc, czr);
     if (!(fminf(t_end, fmaxf(b0, b1)) > fmaxf(t_start, fminf(b0, b1)))) {
         s.mz = -1;
         s.stz = 0;
@@ -149,8 +149,8 @@ __host__ __device__ __forceinline__ void zwalk_init(ZWalk &s, float zeta_c, floa
     const int hb = s.stz > 0 ? s.mz + 1 : s.mz;
     const int lb = hb - s.stz;
     s.hbf = (float)hb - hz;
-    s.lz = (lb >= 0 && lb <= nz) ? cross_at((float)lb - hz, zeta_c, czr) : -INFINITY;
-    s.hzv = (hb >= 0 && hb <= nz) ? cross_at(s.hbf, zeta_c, czr) : INFINITY;
+    s.lz = (lb >= 0 && lb <= nz) ? zeta_cross((float)lb - hz, s.nzc, czr) : -INFINITY;
+    s.hzv = (hb >= 0 && hb <= nz) ? zeta_cross(s.hbf, s.nzc, czr) : INFINITY;
     for (int guard = nz + 2; s.hzv < t_start && guard > 0; --guard) zwalk_step(s);
 }
 
@@ -271,7 +271,7 @@ __host__ __device__ __forceinline__ void trace_rays(const T *__restrict__ vol, i
             m[r] = z.mz;
             const bool c = z.hzv < t1;
             const float nhbf = z.hbf + z.fstz;
-            const float nhzv = cross_at(nhbf, z.zeta_c, z.czr);
+            const float nhzv = zeta_cross(nhbf, z.nzc, z.czr);
             if (c) {
                 z.lz = z.hzv;
                 z.mz += z.stz;

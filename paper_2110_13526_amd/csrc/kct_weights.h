@@ -42,6 +42,13 @@ __host__ __device__ __forceinline__ float zeta_centre(float qz, float tcv, float
 }
 __host__ __device__ __forceinline__ float zeta_inv_slope(float inv_qz, float kz) { return inv_qz * kz; }
 
+// xi at which a ray crosses the zeta-plane h (index frame), from the ray's
+// offset nzc = zeta_offset(zeta_c, czr): one fused multiply-add per plane.
+// The forward's z-walk and the backprojector's candidates take every zeta
+// crossing from these two, so both see the same bits.
+__host__ __device__ __forceinline__ float zeta_offset(float zc, float czr) { return -(zc * czr); }
+__host__ __device__ __forceinline__ float zeta_cross(float h, float nzc, float czr) { return __builtin_fmaf(h, czr, nzc); }
+
 // Length of the ray in mm per unit of xi.  On the GPU the hardware square root
 // (within 1 ulp; one instruction instead of the correctly rounded sequence):
 // every kernel takes L from this function, so L stays one number per ray.
