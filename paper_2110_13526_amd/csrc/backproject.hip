@@ -140,10 +140,14 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                 if (threadIdx.x < 2 * ncol) {
                     const int zr = threadIdx.x < ncol ? nrow : nrow + 1;
                     const int zcol = threadIdx.x < ncol ? (int)threadIdx.x : (int)threadIdx.x - ncol;
+                    // the zero made here (an empty asm keeps the compiler from
+                    // hoisting the record out of the view loop and spilling it)
+                    float zero = 0.0f;
+                    asm volatile("" : "+v"(zero));
                     PixStage<A> z{};
-                    z.nzc = 0.0f;
-                    z.czr = 0.0f;
-                    z.le = (A)0;
+                    z.nzc = zero;
+                    z.czr = zero;
+                    z.le = (A)zero;
                     s_pix[zr * CHC + zcol] = z;
                 }
                 __syncthreads();
