@@ -25,10 +25,10 @@ __device__ __forceinline__ double bwd_block_sum(double v)
 {
     __shared__ double red[4];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    if ((__builtin_amdgcn_workitem_id_x() & 63) == 0) red[__builtin_amdgcn_workitem_id_x() >> 6] = v;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    if (__builtin_amdgcn_workitem_id_x() == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
     return r;
 }
 
@@ -56,8 +56,8 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     const int nb = nbx * nby * nbz;
     const int b = (nb % NXCD == 0) ? (w % NXCD) * (nb / NXCD) + w / NXCD : w;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int ix = bx * BX + (int)(threadIdx.x % BX);
-    const int iy = by * BY + (int)(threadIdx.x / BX);
+    const int ix = bx * BX + (int)(__builtin_amdgcn_workitem_id_x() % BX);
+    const int iy = by * BY + (int)(__builtin_amdgcn_workitem_id_x() / BX);
     const int iz0 = bz * TZB;
     const int nzb = g.nz - iz0 < TZB ? g.nz - iz0 : TZB;
     const bool valid = ix < g.nx && iy < g.ny;
@@ -101,16 +101,21 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
             const int ncol = u1 - cu0 + 1 < CHC ? u1 - cu0 + 1 : CHC;
             for (int cv0 = v0; cv0 <= v1; cv0 += CH_ROWS) {
                 const int nrow = v1 - cv0 + 1 < CH_ROWS ? v1 - cv0 + 1 : CH_ROWS;
+                // the thread index read here (an empty asm keeps the compiler from
+                // hoisting what is derived from it out of the brick loops of the
+                // persistent form, where it spilled)
+                unsigned tid = __builtin_amdgcn_workitem_id_x();
+                asm volatile("" : "+v"(tid));
                 // 2. stage the chunk: per pixel the z-parameters of its ray and L * e,
                 //    per column the in-plane parameters
                 //    (pixel t = r * ncol + c; t steps by 256: r by dr, c by dc, with carry)
                 {
-                    // threadIdx.x / ncol through a reciprocal: (t + 0.5) / ncol lies at least
+                    // tid / ncol through a reciprocal: (t + 0.5) / ncol lies at least
                     // 0.5 / ncol >= 0.01 from an integer, the product's rounding below 1e-4
                     const float rn = __builtin_amdgcn_rcpf((float)ncol);
-                    int r = (int)(((float)threadIdx.x + 0.5f) * rn), c = (int)threadIdx.x - r * ncol;
+                    int r = (int)(((float)tid + 0.5f) * rn), c = (int)tid - r * ncol;
                     const int dr = 256 / ncol, dc = 256 - dr * ncol;
-                    for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
+                    for (int t = (int)tid; t < ncol * nrow; t += 256) {
                         // the projection value first: its load overlaps the parameter loads.
                         // All three are addressed as a uniform base plus a 32-bit byte offset
                         // (one view's projection values span < 2^31 bytes: a detector has
@@ -134,12 +139,12 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                         }
                     }
                 }
-                if (threadIdx.x < ncol) s_col[threadIdx.x] = stage_column(g, vp.dom, ck[cu0 + threadIdx.x]);
+                if (tid < ncol) s_col[tid] = stage_column(g, vp.dom, ck[cu0 + tid]);
                 // two zero rows after the chunk's: the gather reads a voxel's first
                 // candidate row without a branch, and these have weight 0 for any voxel
-                if (threadIdx.x < 2 * ncol) {
-                    const int zr = threadIdx.x < ncol ? nrow : nrow + 1;
-                    const int zcol = threadIdx.x < ncol ? (int)threadIdx.x : (int)threadIdx.x - ncol;
+                if (tid < 2 * ncol) {
+                    const int zr = tid < ncol ? nrow : nrow + 1;
+                    const int zcol = tid < ncol ? (int)tid : (int)tid - ncol;
                     // the zero made here (an empty asm keeps the compiler from
                     // hoisting the record out of the view loop and spilling it)
                     float zero = 0.0f;
@@ -175,7 +180,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
     }
     if (bwd_has_partials<EPI>()) {
         const double bs = bwd_block_sum(sq);
-        if (threadIdx.x == 0) partials[w] = bs;
+        if (__builtin_amdgcn_workitem_id_x() == 0) partials[w] = bs;
     }
 }
 
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward
     constexpr int CHC = ch_cols(TZB);
     __shared__ PixStage<acc_t<T>> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
-    backward_block<T, EPI, TZB, CHC>(g, blockIdx.x, proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
+    backward_block<T, EPI, TZB, CHC>(g, __builtin_amdgcn_workgroup_id_x(), proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
                                      s_col);
 }
 
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(256, 6) void k_backward_v(GeoDev g, const float *__
 {
     __shared__ PixStage<float> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
-    backward_block<float, BWD_PLAIN, TZB, CHC>(g, blockIdx.x, proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
+    backward_block<float, BWD_PLAIN, TZB, CHC>(g, __builtin_amdgcn_workgroup_id_x(), proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
                                                nullptr, s_pix, s_col);
 }
 

@@ -27,7 +27,7 @@ __device__ __forceinline__ int64_t batch_pop(BatchQueue *q)
 {
     __shared__ unsigned s_item;
     __syncthreads();  // the previous item's readers are done with s_item
-    if (threadIdx.x == 0) s_item = atomicAdd(&q->next, 1u);
+    if (__builtin_amdgcn_workitem_id_x() == 0) s_item = atomicAdd(&q->next, 1u);
     __syncthreads();
     return (int64_t)s_item;
 }
@@ -36,10 +36,10 @@ __device__ __forceinline__ int64_t batch_pop(BatchQueue *q)
 // drawn its final item) resets the queue for the next launch of the step.
 __device__ __forceinline__ void batch_exit(BatchQueue *q)
 {
-    if (threadIdx.x == 0) {
+    if (__builtin_amdgcn_workitem_id_x() == 0) {
         __threadfence();
         const unsigned n = atomicAdd(&q->exited, 1u);
-        if (n == gridDim.x - 1) {
+        if (n == __builtin_amdgcn_grid_size_x() / __builtin_amdgcn_workgroup_size_x() - 1) {
             atomicExch(&q->next, 0u);
             atomicExch(&q->exited, 0u);
         }

@@ -32,11 +32,11 @@ __device__ __forceinline__ double block_sum_256(double v)
 {
     __shared__ double red[4];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[w] = v;
+    const int w = __builtin_amdgcn_workitem_id_x() >> 6;
+    if ((__builtin_amdgcn_workitem_id_x() & 63) == 0) red[w] = v;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    if (__builtin_amdgcn_workitem_id_x() == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
     return r;
 }
 
@@ -81,8 +81,8 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
     const int band = (int)(rest / fg.nviews);
     // the wavefront's column, made provably uniform so that the in-plane walk
     // (a function of the column) runs on scalar registers and branches
-    const int iu = cg * FWD_COLS + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = (int)(threadIdx.x & 63);
+    const int iu = cg * FWD_COLS + __builtin_amdgcn_readfirstlane((int)(__builtin_amdgcn_workitem_id_x() >> 6));
+    const int lane = (int)(__builtin_amdgcn_workitem_id_x() & 63);
     ViewParam vp = g.views[k];
     vp.dom = __builtin_amdgcn_readfirstlane(vp.dom);  // uniform: the volume's base and strides follow it
 
@@ -141,7 +141,7 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
     }
     if (EPI != FWD_PLAIN) {
         const double bs = block_sum_256(sq);
-        if (threadIdx.x == 0) partials[w] = bs;
+        if (__builtin_amdgcn_workitem_id_x() == 0) partials[w] = bs;
     }
 }
 
@@ -152,7 +152,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<TV>) != 4 ? 1 : 8) void k_forward
                                                  const int *__restrict__ skip)
 {
     if (skip && *skip) return;
-    forward_block<TV, TP, EPI, FWD_R>(g, blockIdx.x, vol, vol_z, out, aux, sc, partials);
+    forward_block<TV, TP, EPI, FWD_R>(g, __builtin_amdgcn_workgroup_id_x(), vol, vol_z, out, aux, sc, partials);
 }
 
 // One explicit rows-per-lane variant, plain epilogue (the batched form's tuner times these).
@@ -160,7 +160,7 @@ template <typename TV, typename TP, int EPI, int R>
 __global__ __launch_bounds__(256) void k_forward_r(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
                                                    TP *__restrict__ out)
 {
-    forward_block<TV, TP, EPI, R>(g, blockIdx.x, vol, vol_z, out, nullptr, nullptr, nullptr);
+    forward_block<TV, TP, EPI, R>(g, __builtin_amdgcn_workgroup_id_x(), vol, vol_z, out, nullptr, nullptr, nullptr);
 }
 
 int64_t forward_num_blocks(const GeoDev &g)

@@ -61,10 +61,10 @@ __device__ __forceinline__ double tt_block_sum(double v)
 {
     __shared__ double red[4];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    if ((__builtin_amdgcn_workitem_id_x() & 63) == 0) red[__builtin_amdgcn_workitem_id_x() >> 6] = v;
     __syncthreads();
     double r = 0.0;
-    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    if (__builtin_amdgcn_workitem_id_x() == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
     return r;
 }
 
@@ -77,21 +77,21 @@ __global__ __launch_bounds__(256) void k_forward_tt(GeoDev g, const TV *__restri
     if (skip && *skip) return;
     using A = acc_t<TV>;
     const TTFwdGrid fg = tt_fwd_grid(g);
-    const int64_t w = blockIdx.x;
+    const int64_t w = __builtin_amdgcn_workgroup_id_x();
     const int64_t full = fg.nblocks & ~(int64_t)63;
     const int64_t L = w < full ? (w & ~(int64_t)63) + (w % TT_NXCD) * 8 + (w / TT_NXCD) % 8 : w;
     const int cg = (int)(L % fg.ncg);
     const int64_t rest = L / fg.ncg;
     const int k = (int)(rest % fg.nviews);
     const int band = (int)(rest / fg.nviews);
-    const int iu = cg * TT_COLS + (int)(threadIdx.x >> 6);
+    const int iu = cg * TT_COLS + (int)(__builtin_amdgcn_workitem_id_x() >> 6);
     const bool col_ok = iu < g.nu;
     // lane rows: band * 64 TT_R + lane + 64 r
     int iv[TT_R];
     bool ok[TT_R];
 #pragma unroll
     for (int r = 0; r < TT_R; ++r) {
-        iv[r] = band * 64 * TT_R + (int)(threadIdx.x & 63) + 64 * r;
+        iv[r] = band * 64 * TT_R + (int)(__builtin_amdgcn_workitem_id_x() & 63) + 64 * r;
         ok[r] = col_ok && iv[r] < g.nv;
     }
     A acc[TT_R] = {};
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_forward_tt(GeoDev g, const TV *__restri
     }
     if (EPI != FWD_PLAIN) {
         const double bs = tt_block_sum(sq);
-        if (threadIdx.x == 0) partials[blockIdx.x] = bs;
+        if (__builtin_amdgcn_workitem_id_x() == 0) partials[__builtin_amdgcn_workgroup_id_x()] = bs;
     }
 }
 
@@ -126,11 +126,11 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
     __shared__ A s_le[TT_CH_ROWS * TT_CH_COLS];
 
     const int nb = nbx * nby * nbz;
-    const int w = blockIdx.x;
+    const int w = __builtin_amdgcn_workgroup_id_x();
     const int b = (nb % TT_NXCD == 0) ? (w % TT_NXCD) * (nb / TT_NXCD) + w / TT_NXCD : w;
     const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int ix = bx * BX + (int)(threadIdx.x % BX);
-    const int iy = by * BY + (int)(threadIdx.x / BX);
+    const int ix = bx * BX + (int)(__builtin_amdgcn_workitem_id_x() % BX);
+    const int iy = by * BY + (int)(__builtin_amdgcn_workitem_id_x() / BX);
     const int iz0 = bz * TT_TZ;
     const int nzb = g.nz - iz0 < TT_TZ ? g.nz - iz0 : TT_TZ;
     const bool valid = ix < g.nx && iy < g.ny;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
         // without a barrier (the same numbers in all)
         int u0, u1, v0, v1;
         {
-            const int c = threadIdx.x & 7;
+            const int c = __builtin_amdgcn_workitem_id_x() & 7;
             float fu, fv;
             project_point(g, vp, (c & 1) ? wx1 : wx0, (c & 2) ? wy1 : wy0, (c & 4) ? wz1 : wz0, fu, fv);
             float umin = fu, umax = fu, vmin = fv, vmax = fv;
@@ -183,9 +183,9 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
                 const int nrow = v1 - cv0 + 1 < TT_CH_ROWS ? v1 - cv0 + 1 : TT_CH_ROWS;
                 // pixel t = r * ncol + c; t steps by 256: r by dr, c by dc, with carry
                 {
-                    int r = (int)threadIdx.x / ncol, c = (int)threadIdx.x - r * ncol;
+                    int r = (int)__builtin_amdgcn_workitem_id_x() / ncol, c = (int)__builtin_amdgcn_workitem_id_x() - r * ncol;
                     const int dr = 256 / ncol, dc = 256 - dr * ncol;
-                    for (int t = threadIdx.x; t < ncol * nrow; t += 256) {
+                    for (int t = __builtin_amdgcn_workitem_id_x(); t < ncol * nrow; t += 256) {
                         // the projection value first: its load overlaps the parameter loads
                         // (offsets within one view fit in 32 bits: a projection has < 2^31 rays)
                         const A ev = SQ ? (A)0 : to_acc(pk[(unsigned)((cv0 + r) * g.nu + cu0 + c)]);
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) == 4 ? 5 : 2) void k_backward
     }
     if (bwd_has_partials<EPI>()) {
         const double bs = tt_block_sum(sq);
-        if (threadIdx.x == 0) partials[w] = bs;
+        if (__builtin_amdgcn_workitem_id_x() == 0) partials[w] = bs;
     }
 }
 
