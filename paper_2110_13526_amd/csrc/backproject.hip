@@ -221,7 +221,7 @@ static void bwd_grid(const GeoDev &g, int tz, int &nbx, int &nby, int &nbz)
 
 // Backprojection variants of the batched form (BwdVariant): brick depth and
 // staged chunk width.
-__host__ __device__ constexpr int variant_depth(int v) { return v == BWD_V20 ? TZ_DEEP : TZ; }
+__host__ __device__ constexpr int variant_depth(int v) { return v == BWD_VDEEP ? TZ_DEEP : TZ; }
 constexpr int VARIANT_LDS_COLS = 48;  // the widest chunk of the variants
 
 int64_t backward_variant_grid(const GeoDev &g, int variant, int &nbx, int &nby, int &nbz)
@@ -232,13 +232,13 @@ int64_t backward_variant_grid(const GeoDev &g, int variant, int &nbx, int &nby, 
 
 // The variant a single solve would use: its block decomposition (and so its
 // partial sums) is that of kct_cgls_solve.
-int backward_default_variant(const GeoDev &g) { return bwd_depth(g) == TZ_DEEP ? BWD_V20 : BWD_V16; }
+int backward_default_variant(const GeoDev &g) { return bwd_depth(g) == TZ_DEEP ? BWD_VDEEP : BWD_VSHALLOW; }
 
 // One tile (brick) of variant v of instance bi's r = A^T e with |r|^2 partials.
 __device__ __forceinline__ void batch_backward_tile(const BatchInst *bi, int lw, PixStage<float> *s_pix,
                                                     ColStage *s_col)
 {
-    if (bi->bwd_v == BWD_V20)
+    if (bi->bwd_v == BWD_VDEEP)
         backward_block<float, BWD_NORM, TZ_DEEP, 32>(bi->g, lw, bi->e, bi->r, nullptr, bi->sc, bi->part, bi->nbx,
                                                     bi->nby, bi->nbz, nullptr, s_pix, s_col);
     else
@@ -299,7 +299,7 @@ hipError_t launch_backward_variant(const GeoDev &g, int variant, const float *pr
 {
     int nbx, nby, nbz;
     const int64_t nb = backward_variant_grid(g, variant, nbx, nby, nbz);
-    if (variant == BWD_V20)
+    if (variant == BWD_VDEEP)
         hipLaunchKernelGGL((k_backward_v<TZ_DEEP, 32>), dim3((unsigned)nb), dim3(256), 0, st, g, proj, out, nbx, nby,
                            nbz);
     else

@@ -26,7 +26,7 @@
 namespace kct {
 
 constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
-constexpr int TZ_DEEP = 20;                // deeper bricks for large volumes (more voxels share a lane's setup)
+constexpr int TZ_DEEP = 32;                // deeper bricks for large volumes (more voxels share a lane's setup)
 constexpr int CH_ROWS = 32;                // staged shadow chunk: rows, and columns by brick depth
 // Columns of the staged chunk: 32 for the deep bricks of large volumes (whose
 // shadows are at most about 28 x 28 pixels at typical magnifications; the

@@ -252,7 +252,7 @@ struct BatchInst {
 // Backprojection variants of the batched form: brick depth and staged chunk
 // width (columns).  0: 16-deep bricks, 48-column chunks; 1: 20-deep bricks,
 // 32-column chunks (the single solve's choice for large volumes).
-enum BwdVariant { BWD_V16 = 0, BWD_V20 = 1, BWD_VARIANTS = 2 };
+enum BwdVariant { BWD_VSHALLOW = 0, BWD_VDEEP = 1, BWD_VARIANTS = 2 };
 
 enum BatchGrid { BG_FWD = 0, BG_BWD, BG_DIR, BG_STREAM, BG_COUNT };  // item tables, each count + 1 long
 // Tiles per queue item of each persistent step: items must far outnumber the
