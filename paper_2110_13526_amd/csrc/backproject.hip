@@ -40,7 +40,7 @@ template <typename E> __device__ __forceinline__ const E *byte_at(const void *ba
 
 // backward_block runs workgroup w (0 <= w < nbx * nby * nbz) of the
 // backprojection into one volume; its partial sum goes to partials[w].
-// s_pix / s_col: LDS for CH_ROWS x CHC staged pixels (plus two zero rows and a
+// s_pix / s_col: LDS for ch_rows(TZB) x CHC staged pixels (plus two zero rows and a
 // spare record) and CHC columns.
 template <typename T, int EPI, int TZB, int CHC>
 __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *__restrict__ proj,
@@ -50,6 +50,7 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
                                                PixStage<acc_t<T>> *s_pix, ColStage *s_col)
 {
     using A = acc_t<T>;
+    constexpr int CHR = ch_rows(TZB);  // staged rows per chunk
     constexpr bool SQ = EPI == BWD_DIAG || EPI == BWD_DIAG_INV;  // squared weights, e not read
 
     // XCD-aware brick assignment
@@ -99,8 +100,8 @@ __device__ __forceinline__ void backward_block(const GeoDev &g, int w, const T *
         const ColParam *ck = g.cols + (size_t)k * g.nu;
         for (int cu0 = u0; cu0 <= u1; cu0 += CHC) {
             const int ncol = u1 - cu0 + 1 < CHC ? u1 - cu0 + 1 : CHC;
-            for (int cv0 = v0; cv0 <= v1; cv0 += CH_ROWS) {
-                const int nrow = v1 - cv0 + 1 < CH_ROWS ? v1 - cv0 + 1 : CH_ROWS;
+            for (int cv0 = v0; cv0 <= v1; cv0 += CHR) {
+                const int nrow = v1 - cv0 + 1 < CHR ? v1 - cv0 + 1 : CHR;
                 // the thread index read here (an empty asm keeps the compiler from
                 // hoisting what is derived from it out of the brick loops of the
                 // persistent form, where it spilled)
@@ -196,7 +197,7 @@ __global__ __launch_bounds__(256, sizeof(acc_t<T>) != 4 ? 2 : 6) void k_backward
 {
     if (skip && *skip) return;
     constexpr int CHC = ch_cols(TZB);
-    __shared__ PixStage<acc_t<T>> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
+    __shared__ PixStage<acc_t<T>> s_pix[(ch_rows(TZB) + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<T, EPI, TZB, CHC>(g, __builtin_amdgcn_workgroup_id_x(), proj, out, out_z, sc, partials, nbx, nby, nbz, aux, s_pix,
                                      s_col);
@@ -223,6 +224,11 @@ static void bwd_grid(const GeoDev &g, int tz, int &nbx, int &nby, int &nbz)
 // staged chunk width.
 __host__ __device__ constexpr int variant_depth(int v) { return v == BWD_VDEEP ? TZ_DEEP : TZ; }
 constexpr int VARIANT_LDS_COLS = 48;  // the widest chunk of the variants
+// staged records of the largest chunk of the variants
+constexpr int VARIANT_LDS_RECORDS =
+    ((ch_rows(TZ_DEEP) + 2) * ch_cols(TZ_DEEP) > (ch_rows(TZ) + 2) * ch_cols(TZ) ? (ch_rows(TZ_DEEP) + 2) * ch_cols(TZ_DEEP)
+                                                                                  : (ch_rows(TZ) + 2) * ch_cols(TZ)) +
+    NH - 1;
 
 int64_t backward_variant_grid(const GeoDev &g, int variant, int &nbx, int &nby, int &nbz)
 {
@@ -253,7 +259,7 @@ __global__ __launch_bounds__(256, 6) void kp_backward(const BatchInst *__restric
                                                       const int64_t *__restrict__ off, int count,
                                                       BatchQueue *__restrict__ q)
 {
-    __shared__ PixStage<float> s_pix[(CH_ROWS + 2) * VARIANT_LDS_COLS + NH - 1];
+    __shared__ PixStage<float> s_pix[VARIANT_LDS_RECORDS];
     __shared__ ColStage s_col[VARIANT_LDS_COLS];
     const int64_t total = off[count];
     for (;;) {
@@ -289,7 +295,7 @@ template <int TZB, int CHC>
 __global__ __launch_bounds__(256, 6) void k_backward_v(GeoDev g, const float *__restrict__ proj,
                                                        float *__restrict__ out, int nbx, int nby, int nbz)
 {
-    __shared__ PixStage<float> s_pix[(CH_ROWS + 2) * CHC + NH - 1];
+    __shared__ PixStage<float> s_pix[(ch_rows(TZB) + 2) * CHC + NH - 1];
     __shared__ ColStage s_col[CHC];
     backward_block<float, BWD_PLAIN, TZB, CHC>(g, __builtin_amdgcn_workgroup_id_x(), proj, out, nullptr, nullptr, nullptr, nbx, nby, nbz,
                                                nullptr, s_pix, s_col);

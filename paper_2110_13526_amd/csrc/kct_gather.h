@@ -14,7 +14,7 @@
 //      columns (shared by the TZ voxels), per voxel the candidate rows from
 //      the z-range of those rays, and for every candidate the exact weight of
 //      kct_weights.h.
-// The shadow is staged in chunks of at most ch_cols(TZB) x CH_ROWS pixels, so any
+// The shadow is staged in chunks of at most ch_cols(TZB) x ch_rows(TZB) pixels, so any
 // geometry works; typical bricks need one chunk.
 #pragma once
 
@@ -27,12 +27,13 @@ namespace kct {
 
 constexpr int BX = 16, BY = 16, TZ = 16;   // brick; BX * BY = 256 lanes
 constexpr int TZ_DEEP = 32;                // deeper bricks for large volumes (more voxels share a lane's setup)
-constexpr int CH_ROWS = 32;                // staged shadow chunk: rows, and columns by brick depth
+constexpr int CH_ROWS_MAX = 36;            // staged shadow chunk: rows and columns by brick depth
 // Columns of the staged chunk: 32 for the deep bricks of large volumes (whose
 // shadows are at most about 28 x 28 pixels at typical magnifications; the
 // smaller chunk measured faster there), 48 for the shallow bricks, whose
 // volumes tend to have coarse voxels and wide shadows.
 __host__ __device__ constexpr int ch_cols(int tzb) { return tzb == TZ_DEEP ? 32 : 48; }
+__host__ __device__ constexpr int ch_rows(int tzb) { return tzb == TZ_DEEP ? 36 : 32; }
 constexpr int NH = 2;                      // detector columns held in registers at once
 
 struct ColStage {  // per staged detector column: in-plane ray parameters
