@@ -23,7 +23,7 @@
 namespace kct {
 
 constexpr int FWD_COLS = 4;    // detector columns per workgroup (one per wavefront)
-constexpr int FWD_R = 2;       // detector rows per lane (default variant; 1 is the other)
+constexpr int FWD_R = 4;       // detector rows per lane (the batched form's tuner chooses 1 or 2)
 constexpr int NXCD = 8;
 
 // Sum of v over the 256 threads of the workgroup, in a fixed order.  Result is
@@ -146,7 +146,7 @@ __device__ __forceinline__ void forward_block(const GeoDev &g, int64_t w, const 
 }
 
 template <typename TV, typename TP, int EPI>
-__global__ __launch_bounds__(256, sizeof(acc_t<TV>) != 4 ? 1 : 8) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
+__global__ __launch_bounds__(256, sizeof(acc_t<TV>) != 4 ? 1 : (sizeof(TV) == 4 ? 7 : 8)) void k_forward(GeoDev g, const TV *__restrict__ vol, const TV *__restrict__ vol_z,
                                                  TP *__restrict__ out, const TP *__restrict__ aux,
                                                  const Scalars *__restrict__ sc, double *__restrict__ partials,
                                                  const int *__restrict__ skip)
