@@ -183,7 +183,7 @@ kct_status kct_batch_create(const kct_geometry *geoms, int32_t count, kct_batch 
                         KCT_ERR_INVALID_ARG);
         }
         b->geoms.push_back(g);
-        b->fwd_r.push_back(2);  // the single solve's forward variant
+        b->fwd_r.push_back(2);  // two rows per lane until the tuner has timed the instance
         b->bwd_v.push_back(backward_default_variant(g->dev));
         b->order.push_back(i);
     }
